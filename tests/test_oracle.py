@@ -1,0 +1,71 @@
+"""The FP64 oracle against its pins (arXiv 2005.10123, Section 2.1), and planted mistakes that the
+pins must catch.  CPU only."""
+import os
+import subprocess
+
+import pytest
+
+import oracle
+import oracle_pins as P
+
+
+@pytest.fixture(scope="module")
+def lib():
+    oracle.build()
+    return oracle.load(oracle.LIBRARY)
+
+
+@pytest.mark.parametrize("pin", P.ALL_PINS, ids=[p.__name__ for p in P.ALL_PINS])
+def test_pin(lib, pin):
+    pin(lib)
+
+
+# (description, text in hawkes_oracle.c, replacement).  Each is a plausible slip in the oracle.
+MUTANTS = [
+    ("background normaliser (2 pi)^1 instead of (2 pi)^(3/2)",
+     "pow(ORACLE_TWO_PI, 1.5)", "pow(ORACLE_TWO_PI, 1.0)"),
+    ("trigger coefficient theta/omega as printed",
+     "const double ce = theta * omega /", "const double ce = theta / omega /"),
+    ("ties counted as causal", "if (t[j] < t[i]) {", "if (t[j] <= t[i]) {"),
+    ("diagonal background term dropped",
+     "for (long j = 0; j < n; ++j) {\n        const double dx",
+     "for (long j = 0; j < n; ++j) {\n        if (j == i) continue;\n        const double dx"),
+    ("temporal bandwidth replaced by the spatial one",
+     "dt * dt / (2.0 * tt * tt)", "dt * dt / (2.0 * tx * tx)"),
+    ("trigger delay sign flipped", "exp(-omega * dt - r2", "exp(omega * dt - r2"),
+    ("sign of the trigger part of Lambda",
+     ") - theta * expm1(-omega * u);", ") + theta * expm1(-omega * u);"),
+    ("lower limit of the background integral dropped",
+     "norm_cdf(u / tt) - norm_cdf(-t[i] / tt)) - theta", "norm_cdf(u / tt) - 0.5) - theta"),
+    ("tau_t gradient without its Sbt term", "cb * (-Sb / tt + Sbt / (tt * tt * tt)),", "cb * (-Sb / tt),"),
+    ("omega gradient sign", "(Se - omega * Set)", "(Se + omega * Set)"),
+    ("h gradient power", "Ser / (h * h * h)", "Ser / (h * h)"),
+    ("T taken as the last time, not the largest", "if (t[k] > T) T = t[k];", "T = t[k];"),
+    ("x and y mixed up", "const double dy = y[i] - y[j];", "const double dy = y[i] - x[j];"),
+    ("d Lambda / d omega without u", "theta * u * exp(-omega * u)", "theta * exp(-omega * u)"),
+    ("d Lambda / d tau_t sign of the lower-limit term",
+     "(u * norm_pdf(u / tt) + t[i] * norm_pdf(t[i] / tt))",
+     "(u * norm_pdf(u / tt) - t[i] * norm_pdf(t[i] / tt))"),
+    ("pi from the background part", "out->pi = ce * Se / lambda;", "out->pi = cb * Sb / lambda;"),
+    ("Sbr weighted by dt", "Sbr += r2 * b;", "Sbr += dt * b;"),
+    ("Set weighted by r2", "Set += dt * e;", "Set += r2 * e;"),
+]
+
+
+@pytest.mark.parametrize("desc,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(tmp_path, desc, old, new):
+    src = open(oracle.SOURCE).read()
+    assert src.count(old) == 1, f"mutation site not unique: {old!r}"
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = str(tmp_path / "libmutant.so")
+    oracle.build(str(path), so)
+    lib = oracle.load(so)
+    caught = []
+    for pin in P.ALL_PINS:
+        try:
+            pin(lib)
+        except (AssertionError, ValueError, FloatingPointError) as exc:
+            caught.append((pin.__name__, str(exc)[:80]))
+            break
+    assert caught, f"no pin catches: {desc}"
