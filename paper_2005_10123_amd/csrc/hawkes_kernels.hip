@@ -1,0 +1,444 @@
+// hawkes_kernels.hip -- gfx950 kernels of the exact O(N^2) spatiotemporal Hawkes log-likelihood
+// (arXiv 2005.10123, Section 2.1, the log-likelihood equation) and its gradient.
+//
+// Three kernels per evaluation, each able to serve several requests in one launch:
+//
+//  1. pair_fp32c / pair_fp64 -- the pairwise pass.  For every row (event) i it sums over all
+//     columns j the unnormalised background kernel B_ij = exp(-r^2/(2 tau_x^2) - dt^2/(2 tau_t^2))
+//     (j = i included) and, for causal columns j < cut[i] (t_j < t_i), the unnormalised trigger
+//     E_ij = exp(-omega dt - r^2/(2 h^2)).  With the gradient it also sums r^2 B, dt^2 B, dt E and
+//     r^2 E.  Running sums only, never the N x N terms (the paper's fourth rule of thumb,
+//     Section 3.1).  Layout: a block = 4 waves; each lane keeps kRowsPerLane rows in registers;
+//     the block streams column tiles of kTile events through LDS and every lane reads each column
+//     as a broadcast, so one LDS read feeds 64 x kRowsPerLane pair terms.  The column range is cut
+//     into `splits` pieces so that even one evaluation fills the 256 CUs; each (row block, column
+//     piece) writes its own partial sums, so the result never depends on scheduling.  Because rows
+//     and columns are time-sorted, a whole tile is either fully causal for a wave (no mask), fully
+//     non-causal (no trigger work at all), or straddles the wave's rows (masked exponent).
+//  2. epilogue -- per event, in binary64: combine the partial sums in a fixed order,
+//     lambda_i = c_b S_b + c_e S_e, Lambda_i (closed form of Section 2.1), ell_i = log lambda_i -
+//     Lambda_i and the six gradient terms; then a fixed-shape tree reduction per block.
+//  3. final -- one block per request sums the block partials in a fixed order (the paper's second
+//     kernel, Algorithm 3 step 2, made deterministic).
+//
+// The exponentials are base 2 with log2(e) folded into the coefficients: the FP32C path uses the
+// hardware v_exp_f32, the FP64 path the exp2 below.  There is no matrix-core work: with two
+// spatial dimensions the pair terms are not a dense contraction.
+#include "hawkes_internal.h"
+
+#include <math.h>
+
+namespace hawkes {
+namespace {
+
+constexpr int kChunk = 32;  // pair terms summed plainly in binary32 before a compensated merge
+
+enum Mode : int { kNone = 0, kFull = 1, kMask = 2 };
+
+// Keep a wave-uniform constant in a vector register: two-operand VALU ops whose operands are all
+// VGPRs issue faster on gfx950 than ones reading a scalar register.
+__device__ __forceinline__ float in_vgpr(float v)
+{
+    float r;
+    asm("v_mov_b32 %0, %1" : "=v"(r) : "v"(v));
+    return r;
+}
+
+// s + c += p with the rounding error of s + p kept exactly in c (Knuth's TwoSum).
+__device__ __forceinline__ void two_sum_into(float& s, float& c, float p)
+{
+    const float t = s + p;
+    const float bp = t - s;
+    const float err = (s - (t - bp)) + (p - bp);
+    s = t;
+    c += err;
+}
+
+// 2^a in binary64 for a <= 0 (a = -inf allowed).  Range reduction a = k + f, k = rint(a),
+// |f| <= 1/2, then 2^f = exp(f ln 2) by its Taylor polynomial of degree 12 (truncation error
+// below 2e-16 relative on |f ln 2| <= 0.347), scaled by 2^k.  Arguments below -1100 give exactly 0.
+__device__ __forceinline__ double exp2_f64(double a)
+{
+    a = fmax(a, -1100.0);
+    const double k = rint(a);
+    const double f = a - k;
+    double p = 2.5678435993488205142e-11;
+    p = fma(p, f, 4.4455382718708114976e-10);
+    p = fma(p, f, 7.0549116208011233299e-09);
+    p = fma(p, f, 1.0178086009239699727e-07);
+    p = fma(p, f, 1.3215486790144309488e-06);
+    p = fma(p, f, 1.5252733804059840280e-05);
+    p = fma(p, f, 1.5403530393381609954e-04);
+    p = fma(p, f, 1.3333558146428443423e-03);
+    p = fma(p, f, 9.6181291076284771620e-03);
+    p = fma(p, f, 5.5504108664821579953e-02);
+    p = fma(p, f, 2.4022650695910071233e-01);
+    p = fma(p, f, 6.9314718055994530942e-01);
+    p = fma(p, f, 1.0);
+    return ldexp(p, (int)k);
+}
+
+template <typename Req>
+__device__ __forceinline__ int find_request(const Req* r, int nreq, int item)
+{
+    int q = 0;
+#pragma unroll 1
+    for (int k = 1; k < nreq; ++k)
+        if (item >= r[k].item_begin) q = k;
+    return q;
+}
+
+// ------------------------------------------------------------------------------------------------
+// FP32C pairwise pass.
+template <int MODE, bool GRAD>
+__device__ __forceinline__ void chunk_fp32(const float4* __restrict__ sj, int jbase,
+                                           const float (&xh)[kRowsPerLane], const float (&yh)[kRowsPerLane],
+                                           const float (&th)[kRowsPerLane], const float (&xl)[kRowsPerLane],
+                                           const float (&yl)[kRowsPerLane], const float (&tl)[kRowsPerLane],
+                                           const int (&ct)[kRowsPerLane], float nab, float nbb,
+                                           float nae, float nbe, float (&p)[6][kRowsPerLane])
+{
+    constexpr int R = kRowsPerLane;
+#pragma unroll 2
+    for (int jj = 0; jj < kChunk; ++jj) {
+        const float4 hi = sj[2 * jj];
+        const float4 lo = sj[2 * jj + 1];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const float dx = (xh[r] - hi.x) + (xl[r] - lo.x);
+            const float dy = (yh[r] - hi.y) + (yl[r] - lo.y);
+            const float dt = (th[r] - hi.z) + (tl[r] - lo.z);
+            const float r2 = fmaf(dx, dx, dy * dy);
+            const float dt2 = dt * dt;
+            const float b = __builtin_amdgcn_exp2f(fmaf(r2, nab, dt2 * nbb));
+            p[0][r] += b;
+            if (GRAD) {
+                p[1][r] = fmaf(r2, b, p[1][r]);
+                p[2][r] = fmaf(dt2, b, p[2][r]);
+            }
+            if (MODE != kNone) {
+                float ae = fmaf(r2, nae, dt * nbe);
+                if (MODE == kMask) ae = (jbase + jj < ct[r]) ? ae : -INFINITY;
+                const float e = __builtin_amdgcn_exp2f(ae);
+                const int ke = GRAD ? 3 : 1;
+                p[ke][r] += e;
+                if (GRAD) {
+                    p[4][r] = fmaf(dt, e, p[4][r]);
+                    p[5][r] = fmaf(r2, e, p[5][r]);
+                }
+            }
+        }
+    }
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
+{
+    constexpr int R = kRowsPerLane;
+    constexpr int K = GRAD ? 6 : 2;
+    __shared__ float4 sj[2 * kTile];
+
+    const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
+    const PairReq& rq = batch.r[q];
+    const int local = (int)blockIdx.x - rq.item_begin;
+    const int rb = rq.row_blocks - 1 - local / rq.splits;  // latest (heaviest) rows first
+    const int sp = local % rq.splits;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = rq.n;
+    const int wrow0 = rb * kRowsPerBlock + wave * (64 * R);
+    const bool active = wrow0 < n;  // wave-uniform
+
+    float xh[R], yh[R], th[R], xl[R], yl[R], tl[R];
+    int ct[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = wrow0 + 64 * r + lane;
+        const float4 a = rq.ev32[2 * (size_t)i];
+        const float4 b = rq.ev32[2 * (size_t)i + 1];
+        xh[r] = a.x; yh[r] = a.y; th[r] = a.z;
+        xl[r] = b.x; yl[r] = b.y; tl[r] = b.z;
+        ct[r] = rq.cut[i];
+    }
+    // Rows are time-sorted, so the causal counts of the wave's rows lie in [clo, chi].
+    const int clo = __builtin_amdgcn_readfirstlane(rq.cut[min(wrow0, n - 1)]);
+    const int chi = __builtin_amdgcn_readfirstlane(rq.cut[min(wrow0 + 64 * R - 1, n - 1)]);
+    const float nab = in_vgpr(rq.nab), nbb = in_vgpr(rq.nbb);
+    const float nae = in_vgpr(rq.nae), nbe = in_vgpr(rq.nbe);
+
+    float s[K][R], c[K][R];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[k][r] = c[k][r] = 0.0f;
+
+    const int tiles = rq.npad / kTile;
+    const int t0 = sp * rq.tiles_per_split;
+    const int t1 = min(t0 + rq.tiles_per_split, tiles);
+    for (int tile = t0; tile < t1; ++tile) {
+        const int j0 = tile * kTile;
+        __syncthreads();
+        const float4* src = rq.ev32 + 2 * (size_t)(j0 + threadIdx.x);
+        sj[2 * threadIdx.x] = src[0];
+        sj[2 * threadIdx.x + 1] = src[1];
+        __syncthreads();
+        if (!active) continue;
+        const int mode = (j0 + kTile <= clo) ? kFull : (j0 >= chi ? kNone : kMask);
+        for (int ch = 0; ch < kTile; ch += kChunk) {
+            float p[6][R];
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r) p[k][r] = 0.0f;
+            const float4* tj = sj + 2 * ch;
+            if (mode == kNone)
+                chunk_fp32<kNone, GRAD>(tj, j0 + ch, xh, yh, th, xl, yl, tl, ct, nab, nbb, nae, nbe, p);
+            else if (mode == kFull)
+                chunk_fp32<kFull, GRAD>(tj, j0 + ch, xh, yh, th, xl, yl, tl, ct, nab, nbb, nae, nbe, p);
+            else
+                chunk_fp32<kMask, GRAD>(tj, j0 + ch, xh, yh, th, xl, yl, tl, ct, nab, nbb, nae, nbe, p);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r) two_sum_into(s[k][r], c[k][r], p[k][r]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = wrow0 + 64 * r + lane;
+            rq.part[((size_t)sp * K + k) * rq.npad + i] = (double)s[k][r] + (double)c[k][r];
+        }
+}
+
+// ------------------------------------------------------------------------------------------------
+// FP64 pairwise pass: same decomposition, binary64 throughout, plain running sums.
+template <int MODE, bool GRAD>
+__device__ __forceinline__ void tile_fp64(const double4* __restrict__ sj, int jbase,
+                                          const double (&x)[kRowsPerLane], const double (&y)[kRowsPerLane],
+                                          const double (&t)[kRowsPerLane], const int (&ct)[kRowsPerLane],
+                                          double nab, double nbb, double nae, double nbe,
+                                          double (&a)[6][kRowsPerLane])
+{
+    constexpr int R = kRowsPerLane;
+#pragma unroll 1
+    for (int jj = 0; jj < kTile; ++jj) {
+        const double4 e = sj[jj];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const double dx = x[r] - e.x;
+            const double dy = y[r] - e.y;
+            const double dt = t[r] - e.z;
+            const double r2 = fma(dx, dx, dy * dy);
+            const double dt2 = dt * dt;
+            const double b = exp2_f64(fma(r2, nab, dt2 * nbb));
+            a[0][r] += b;
+            if (GRAD) {
+                a[1][r] = fma(r2, b, a[1][r]);
+                a[2][r] = fma(dt2, b, a[2][r]);
+            }
+            if (MODE != kNone) {
+                double ae = fma(r2, nae, dt * nbe);
+                if (MODE == kMask) ae = (jbase + jj < ct[r]) ? ae : -INFINITY;
+                const double ex = exp2_f64(ae);
+                const int ke = GRAD ? 3 : 1;
+                a[ke][r] += ex;
+                if (GRAD) {
+                    a[4][r] = fma(dt, ex, a[4][r]);
+                    a[5][r] = fma(r2, ex, a[5][r]);
+                }
+            }
+        }
+    }
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(kThreads) void pair_fp64(const PairBatch batch)
+{
+    constexpr int R = kRowsPerLane;
+    constexpr int K = GRAD ? 6 : 2;
+    __shared__ double4 sj[kTile];
+
+    const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
+    const PairReq& rq = batch.r[q];
+    const int local = (int)blockIdx.x - rq.item_begin;
+    const int rb = rq.row_blocks - 1 - local / rq.splits;
+    const int sp = local % rq.splits;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = rq.n;
+    const int wrow0 = rb * kRowsPerBlock + wave * (64 * R);
+    const bool active = wrow0 < n;
+
+    double x[R], y[R], t[R];
+    int ct[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = wrow0 + 64 * r + lane;
+        const double4 e = rq.ev64[i];
+        x[r] = e.x; y[r] = e.y; t[r] = e.z;
+        ct[r] = rq.cut[i];
+    }
+    const int clo = __builtin_amdgcn_readfirstlane(rq.cut[min(wrow0, n - 1)]);
+    const int chi = __builtin_amdgcn_readfirstlane(rq.cut[min(wrow0 + 64 * R - 1, n - 1)]);
+
+    double a[6][R];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[k][r] = 0.0;
+
+    const int tiles = rq.npad / kTile;
+    const int t0 = sp * rq.tiles_per_split;
+    const int t1 = min(t0 + rq.tiles_per_split, tiles);
+    for (int tile = t0; tile < t1; ++tile) {
+        const int j0 = tile * kTile;
+        __syncthreads();
+        sj[threadIdx.x] = rq.ev64[j0 + threadIdx.x];
+        __syncthreads();
+        if (!active) continue;
+        const int mode = (j0 + kTile <= clo) ? kFull : (j0 >= chi ? kNone : kMask);
+        if (mode == kNone)
+            tile_fp64<kNone, GRAD>(sj, j0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a);
+        else if (mode == kFull)
+            tile_fp64<kFull, GRAD>(sj, j0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a);
+        else
+            tile_fp64<kMask, GRAD>(sj, j0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int ka = GRAD ? k : (k == 0 ? 0 : 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = wrow0 + 64 * r + lane;
+            rq.part[((size_t)sp * K + k) * rq.npad + i] = a[ka][r];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
+__device__ __forceinline__ double std_normal_cdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
+__device__ __forceinline__ double std_normal_pdf(double z) { return exp(-0.5 * z * z) * 0.39894228040143267794; }
+
+// Fixed-shape tree over the block: v[m] of every thread summed into thread 0's v[m].
+__device__ __forceinline__ void block_sum7(double (&v)[7], double (*red)[kThreads])
+{
+#pragma unroll
+    for (int m = 0; m < 7; ++m) red[m][threadIdx.x] = v[m];
+    __syncthreads();
+    for (int stride = kThreads / 2; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride)
+#pragma unroll
+            for (int m = 0; m < 7; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + stride];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < 7; ++m) v[m] = red[m][0];
+}
+
+__global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
+{
+    __shared__ double red[7][kThreads];
+    const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
+    const EpiReq& rq = batch.r[q];
+    const int blk = (int)blockIdx.x - rq.item_begin;
+    const int i = blk * kThreads + threadIdx.x;
+    const int K = rq.grad ? 6 : 2;
+
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (i < rq.n) {
+        double S[6] = {0, 0, 0, 0, 0, 0};  // Sb, Sbr, Sbt, Se, Set, Ser
+        for (int s = 0; s < rq.splits; ++s) {
+            const double* ps = rq.part + (size_t)s * K * rq.npad + i;
+            if (rq.grad) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) S[k] += ps[(size_t)k * rq.npad];
+            } else {
+                S[0] += ps[0];
+                S[3] += ps[rq.npad];
+            }
+        }
+        const double ti = rq.ev64[i].z;
+        const double mu0 = rq.mu0, tx = rq.tau_x, tt = rq.tau_t, th = rq.theta, om = rq.omega, h = rq.h;
+        const double lam = rq.cb * S[0] + rq.ce * S[3];
+        const double u = rq.T - ti;
+        const double bg_int = std_normal_cdf(u / tt) - std_normal_cdf(-ti / tt);
+        const double Lam = mu0 * bg_int - th * expm1(-om * u);
+        const double ell = log(lam) - Lam;
+        v[0] = ell;
+        double g[6] = {0, 0, 0, 0, 0, 0};
+        if (rq.grad) {
+            const double inv = 1.0 / lam;
+            const double k2pih2 = 1.0 / (6.28318530717958647693 * h * h);
+            g[0] = rq.cb * S[0] / mu0 * inv - bg_int;
+            g[1] = rq.cb * (-2.0 * S[0] / tx + S[1] / (tx * tx * tx)) * inv;
+            g[2] = rq.cb * (-S[0] / tt + S[2] / (tt * tt * tt)) * inv
+                 + (mu0 / (tt * tt)) * (u * std_normal_pdf(u / tt) + ti * std_normal_pdf(ti / tt));
+            g[3] = om * k2pih2 * S[3] * inv + expm1(-om * u);
+            g[4] = th * k2pih2 * (S[3] - om * S[4]) * inv - th * u * exp(-om * u);
+            g[5] = rq.ce * (-2.0 * S[3] / h + S[5] / (h * h * h)) * inv;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) v[1 + p] = g[p];
+        }
+        if (rq.rows_out) {
+            double* o = rq.rows_out + (size_t)i * kRowOut;
+            o[0] = lam;
+            o[1] = Lam;
+            o[2] = ell;
+            o[3] = rq.ce * S[3] / lam;
+#pragma unroll
+            for (int p = 0; p < 6; ++p) o[4 + p] = g[p];
+        }
+    }
+    block_sum7(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) rq.block_part[(size_t)blk * 7 + m] = v[m];
+}
+
+__global__ __launch_bounds__(kThreads) void final_sum(const EpiBatch batch)
+{
+    __shared__ double red[7][kThreads];
+    const EpiReq& rq = batch.r[blockIdx.x];
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < rq.nblocks; b += kThreads)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) v[m] += rq.block_part[(size_t)b * 7 + m];
+    block_sum7(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) rq.out7[m] = v[m];
+}
+
+}  // namespace
+
+hipError_t launch_pair(const PairBatch& b, int precision, bool grad, hipStream_t s)
+{
+    if (b.total_items <= 0) return hipSuccess;
+    const dim3 grid(b.total_items), block(kThreads);
+    if (precision == kFP32C) {
+        if (grad) pair_fp32c<true><<<grid, block, 0, s>>>(b);
+        else pair_fp32c<false><<<grid, block, 0, s>>>(b);
+    } else {
+        if (grad) pair_fp64<true><<<grid, block, 0, s>>>(b);
+        else pair_fp64<false><<<grid, block, 0, s>>>(b);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_epilogue(const EpiBatch& b, hipStream_t s)
+{
+    if (b.total_items <= 0) return hipSuccess;
+    epilogue<<<dim3(b.total_items), dim3(kThreads), 0, s>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_final(const EpiBatch& b, hipStream_t s)
+{
+    if (b.nreq <= 0) return hipSuccess;
+    final_sum<<<dim3(b.nreq), dim3(kThreads), 0, s>>>(b);
+    return hipGetLastError();
+}
+
+}  // namespace hawkes

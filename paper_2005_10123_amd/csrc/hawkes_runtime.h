@@ -1,0 +1,92 @@
+// hawkes_runtime.h -- host-side state of a libhawkes context (not part of the public ABI).
+#pragma once
+
+#include "../../include/hawkes.h"
+#include "hawkes_internal.h"
+
+#include <atomic>
+#include <condition_variable>
+#include <cstdint>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+namespace hawkes {
+
+struct Dataset {
+    int32_t id = -1;
+    int64_t n = 0;
+    int npad = 0;
+    float4* ev32 = nullptr;
+    double4* ev64 = nullptr;
+    int* cut = nullptr;
+    size_t bytes = 0;
+    std::vector<int> perm;  // sorted position -> caller index
+    double T = 0.0;         // largest event time
+    int inflight = 0;       // submitted requests not yet completed
+};
+
+// How one evaluation is cut into blocks; a function of (n, grad) only, so a request's arithmetic
+// is identical whether it runs alone, blocking, or batched with others.
+struct Plan {
+    int row_blocks = 0, splits = 0, tiles_per_split = 0, K = 0, epi_blocks = 0;
+    size_t part_doubles = 0;
+};
+
+struct Scratch {
+    char* base = nullptr;
+    size_t bytes = 0;
+    hawkes_status reserve(hawkes_ctx* c, size_t need);
+    void release(hawkes_ctx* c);
+};
+
+struct Server;  // hawkes_serving.hip
+
+}  // namespace hawkes
+
+struct hawkes_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    size_t used = 0;  // device bytes held (datasets + scratch); guarded by mu
+    std::mutex mu;    // datasets, budget, blocking scratch, profiling
+    std::map<int32_t, std::unique_ptr<hawkes::Dataset>> datasets;
+    int32_t next_id = 0;
+    hawkes::Scratch blk;       // scratch of blocking and device calls
+    hipEvent_t blk_free = nullptr;  // recorded after the last use of blk
+    double* h_out7 = nullptr;  // pinned
+    bool poisoned = false;
+    bool profile = false;
+    bool prof_pending = false;
+    hipEvent_t prof_ev[2] = {nullptr, nullptr};
+    double pair_ms = 0.0;
+    int64_t pair_launches = 0;
+    hawkes::Server* server = nullptr;
+};
+
+namespace hawkes {
+
+extern thread_local std::string g_last_error;
+hawkes_status fail(hawkes_status code, const char* fmt, ...);
+hawkes_status hip_fail(hipError_t e, const char* what);
+hawkes_status check_params(const hawkes_params* p);
+Plan make_plan(int64_t n, int npad, bool grad);
+size_t scratch_bytes(const Plan& pl, int64_t n, bool rows);
+void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, PairReq& r);
+void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, EpiReq& e);
+void carve(char* base, const Plan& pl, int64_t n, bool rows, double** part, double** block_part, double** out7,
+           double** rows_out);
+hawkes_status dev_alloc(hawkes_ctx* c, void** p, size_t bytes);
+void dev_free(hawkes_ctx* c, void* p, size_t bytes);
+Dataset* find_dataset(hawkes_ctx* c, int32_t id);
+void free_dataset(hawkes_ctx* c, Dataset& d);
+
+hawkes_status server_start(hawkes_ctx* c);
+void server_stop(hawkes_ctx* c);
+
+}  // namespace hawkes

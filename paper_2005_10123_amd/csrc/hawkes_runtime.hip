@@ -1,0 +1,580 @@
+// hawkes_runtime.hip -- host runtime behind include/hawkes.h: contexts, the dataset registry,
+// parameter folding, evaluation plans, scratch and budget accounting, blocking and asynchronous
+// evaluation.  The batched serving loop lives in hawkes_serving.hip.
+#include "hawkes_runtime.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+
+namespace hawkes {
+
+thread_local std::string g_last_error;
+
+hawkes_status fail(hawkes_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+hawkes_status check_params(const hawkes_params* p)
+{
+    if (!p) return fail(HAWKES_EINVAL, "params is NULL");
+    const double v[6] = {p->mu0, p->tau_x, p->tau_t, p->theta, p->omega, p->h};
+    static const char* names[6] = {"mu0", "tau_x", "tau_t", "theta", "omega", "h"};
+    for (int k = 0; k < 6; ++k) {
+        if (!std::isfinite(v[k])) return fail(HAWKES_EINVAL, "%s is not finite", names[k]);
+        if (v[k] > 1e12) return fail(HAWKES_EINVAL, "%s = %g exceeds 1e12", names[k], v[k]);
+        if (k == 3 ? v[k] < 0.0 : v[k] <= 0.0)
+            return fail(HAWKES_EINVAL, "%s = %g is outside its domain", names[k], v[k]);
+    }
+    return HAWKES_OK;
+}
+
+Plan make_plan(int64_t n, int npad, bool grad)
+{
+    Plan pl;
+    pl.row_blocks = npad / kRowsPerBlock;
+    const int tiles = npad / kTile;
+    // About eight blocks per compute unit: enough that the spread of per-block work (later rows
+    // have more causal columns) leaves a short tail.
+    const int target_blocks = 2048;
+    int splits = (target_blocks + pl.row_blocks - 1) / pl.row_blocks;
+    splits = std::max(1, std::min(splits, std::min(kMaxSplits, tiles)));
+    pl.tiles_per_split = (tiles + splits - 1) / splits;
+    pl.splits = (tiles + pl.tiles_per_split - 1) / pl.tiles_per_split;
+    pl.K = grad ? 6 : 2;
+    pl.part_doubles = (size_t)pl.splits * pl.K * npad;
+    pl.epi_blocks = (int)((n + kThreads - 1) / kThreads);
+    return pl;
+}
+
+size_t scratch_bytes(const Plan& pl, int64_t n, bool rows)
+{
+    size_t b = pl.part_doubles * sizeof(double) + (size_t)pl.epi_blocks * 7 * sizeof(double) + 8 * sizeof(double);
+    if (rows) b += (size_t)n * kRowOut * sizeof(double);
+    return b;
+}
+
+// Base-2 exponent coefficients, negated: B = 2^(nab r^2 + nbb dt^2), E = 2^(nae r^2 + nbe dt).
+void fold(const hawkes_params& p, PairReq& r)
+{
+    const double log2e = 1.44269504088896340736;
+    r.nab64 = -log2e / (2.0 * p.tau_x * p.tau_x);
+    r.nbb64 = -log2e / (2.0 * p.tau_t * p.tau_t);
+    r.nae64 = -log2e / (2.0 * p.h * p.h);
+    r.nbe64 = -log2e * p.omega;
+    r.nab = (float)r.nab64;
+    r.nbb = (float)r.nbb64;
+    r.nae = (float)r.nae64;
+    r.nbe = (float)r.nbe64;
+}
+
+void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, EpiReq& e)
+{
+    const double two_pi = 6.28318530717958647693;
+    e.ev64 = d.ev64;
+    e.n = (int)d.n;
+    e.npad = d.npad;
+    e.splits = pl.splits;
+    e.grad = grad ? 1 : 0;
+    e.nblocks = pl.epi_blocks;
+    e.T = d.T;
+    e.mu0 = p.mu0;
+    e.tau_x = p.tau_x;
+    e.tau_t = p.tau_t;
+    e.theta = p.theta;
+    e.omega = p.omega;
+    e.h = p.h;
+    e.cb = p.mu0 / (std::pow(two_pi, 1.5) * p.tau_x * p.tau_x * p.tau_t);
+    e.ce = p.theta * p.omega / (two_pi * p.h * p.h);
+}
+
+void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, PairReq& r)
+{
+    r.ev32 = d.ev32;
+    r.ev64 = d.ev64;
+    r.cut = d.cut;
+    r.n = (int)d.n;
+    r.npad = d.npad;
+    r.row_blocks = pl.row_blocks;
+    r.splits = pl.splits;
+    r.tiles_per_split = pl.tiles_per_split;
+    fold(p, r);
+}
+
+hawkes_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(HAWKES_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Budgeted device allocation; `used` is the caller-held running total.
+hawkes_status dev_alloc(hawkes_ctx* c, void** p, size_t bytes)
+{
+    if (c->used + bytes > c->budget)
+        return fail(HAWKES_ENOMEM, "HBM budget exceeded: %zu used + %zu requested > %zu", c->used, bytes, c->budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(HAWKES_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    c->used += bytes;
+    return HAWKES_OK;
+}
+
+void dev_free(hawkes_ctx* c, void* p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    c->used -= bytes;
+}
+
+hawkes_status Scratch::reserve(hawkes_ctx* c, size_t need)
+{
+    if (need <= bytes) return HAWKES_OK;
+    if (base) {
+        // The previous user of this scratch may still run on the device.
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        dev_free(c, base, bytes);
+        base = nullptr;
+        bytes = 0;
+    }
+    void* p = nullptr;
+    hawkes_status st = dev_alloc(c, &p, need);
+    if (st != HAWKES_OK) return st;
+    base = (char*)p;
+    bytes = need;
+    return HAWKES_OK;
+}
+
+void Scratch::release(hawkes_ctx* c)
+{
+    dev_free(c, base, bytes);
+    base = nullptr;
+    bytes = 0;
+}
+
+// Carve one evaluation's scratch: partial sums, block partials, 7 result doubles, per-row output.
+void carve(char* base, const Plan& pl, int64_t n, bool rows, double** part, double** block_part,
+           double** out7, double** rows_out)
+{
+    double* p = (double*)base;
+    *part = p;
+    p += pl.part_doubles;
+    *block_part = p;
+    p += (size_t)pl.epi_blocks * 7;
+    *out7 = p;
+    p += 8;
+    *rows_out = rows ? p : nullptr;
+}
+
+hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params& p, int precision, bool grad,
+                           char* scratch, double* out7_override, double** out7_used, double** rows_out,
+                           bool want_rows, hipStream_t s)
+{
+    const Plan pl = make_plan(d.n, d.npad, grad);
+    double *part, *bp, *out7, *rows;
+    carve(scratch, pl, d.n, want_rows, &part, &bp, &out7, &rows);
+    if (out7_override) out7 = out7_override;
+
+    PairBatch pb;
+    memset(&pb, 0, sizeof pb);
+    fill_pair(p, d, pl, pb.r[0]);
+    pb.r[0].part = part;
+    pb.r[0].item_begin = 0;
+    pb.nreq = 1;
+    pb.total_items = pl.row_blocks * pl.splits;
+
+    EpiBatch eb;
+    memset(&eb, 0, sizeof eb);
+    fill_epi(p, d, pl, grad, eb.r[0]);
+    eb.r[0].part = part;
+    eb.r[0].block_part = bp;
+    eb.r[0].out7 = out7;
+    eb.r[0].rows_out = rows;
+    eb.r[0].item_begin = 0;
+    eb.nreq = 1;
+    eb.total_items = pl.epi_blocks;
+
+    hipError_t e;
+    if (c->profile) {
+        e = hipEventRecord(c->prof_ev[0], s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    e = launch_pair(pb, precision, grad, s);
+    if (e != hipSuccess) return hip_fail(e, "pair kernel launch");
+    if (c->profile) {
+        e = hipEventRecord(c->prof_ev[1], s);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        c->prof_pending = true;
+    }
+    e = launch_epilogue(eb, s);
+    if (e != hipSuccess) return hip_fail(e, "epilogue launch");
+    e = launch_final(eb, s);
+    if (e != hipSuccess) return hip_fail(e, "final reduction launch");
+    if (out7_used) *out7_used = out7;
+    if (rows_out) *rows_out = rows;
+    return HAWKES_OK;
+}
+
+// Adds the last profiled pair-kernel time once the stream has passed it.
+void collect_profile(hawkes_ctx* c)
+{
+    if (!c->prof_pending) return;
+    float ms = 0.0f;
+    if (hipEventSynchronize(c->prof_ev[1]) == hipSuccess &&
+        hipEventElapsedTime(&ms, c->prof_ev[0], c->prof_ev[1]) == hipSuccess) {
+        c->pair_ms += ms;
+        c->pair_launches += 1;
+    }
+    c->prof_pending = false;
+}
+
+hawkes_status begin_call(hawkes_ctx* c)
+{
+    if (!c) return fail(HAWKES_EINVAL, "ctx is NULL");
+    if (c->poisoned) return fail(HAWKES_EDEVICE, "context is unusable after an earlier device failure");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return HAWKES_OK;
+}
+
+hawkes_status poison(hawkes_ctx* c, hawkes_status st)
+{
+    if (st == HAWKES_EDEVICE) c->poisoned = true;
+    return st;
+}
+
+Dataset* find_dataset(hawkes_ctx* c, int32_t id)
+{
+    auto it = c->datasets.find(id);
+    return it == c->datasets.end() ? nullptr : it->second.get();
+}
+
+// Shared body of the blocking calls.  Holds the context lock for the whole evaluation.
+hawkes_status blocking_eval(hawkes_ctx* c, int32_t id, const hawkes_params* p, int precision, bool grad,
+                            double out7[7], double* host_rows)
+{
+    hawkes_status st = begin_call(c);
+    if (st != HAWKES_OK) return st;
+    if ((st = check_params(p)) != HAWKES_OK) return st;
+    if (precision != HAWKES_FP64 && precision != HAWKES_FP32C)
+        return fail(HAWKES_EINVAL, "precision %d is neither HAWKES_FP64 nor HAWKES_FP32C", precision);
+    std::lock_guard<std::mutex> lk(c->mu);
+    Dataset* d = find_dataset(c, id);
+    if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
+    const bool want_rows = host_rows != nullptr;
+    const Plan pl = make_plan(d->n, d->npad, grad);
+    if ((st = c->blk.reserve(c, scratch_bytes(pl, d->n, want_rows))) != HAWKES_OK) return st;
+    hipStream_t s = c->stream;
+    hipError_t e = hipStreamWaitEvent(s, c->blk_free, 0);
+    if (e != hipSuccess) return poison(c, hip_fail(e, "hipStreamWaitEvent"));
+    double *dout7 = nullptr, *drows = nullptr;
+    st = enqueue_eval(c, *d, *p, precision, grad, c->blk.base, nullptr, &dout7, &drows, want_rows, s);
+    if (st != HAWKES_OK) return poison(c, st);
+    e = hipMemcpyAsync(c->h_out7, dout7, 7 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return poison(c, hip_fail(e, "hipMemcpyAsync"));
+    std::vector<double> sorted_rows;
+    if (want_rows) {
+        sorted_rows.resize((size_t)d->n * kRowOut);
+        e = hipMemcpyAsync(sorted_rows.data(), drows, sorted_rows.size() * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return poison(c, hip_fail(e, "hipMemcpyAsync"));
+    }
+    e = hipEventRecord(c->blk_free, s);
+    if (e != hipSuccess) return poison(c, hip_fail(e, "hipEventRecord"));
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return poison(c, hip_fail(e, "hipStreamSynchronize"));
+    collect_profile(c);
+    memcpy(out7, c->h_out7, 7 * sizeof(double));
+    if (want_rows)
+        for (int64_t k = 0; k < d->n; ++k)
+            memcpy(host_rows + (size_t)d->perm[k] * kRowOut, sorted_rows.data() + (size_t)k * kRowOut,
+                   kRowOut * sizeof(double));
+    return HAWKES_OK;
+}
+
+hawkes_status build_dataset(hawkes_ctx* c, const double* x, const double* y, const double* t, int64_t n,
+                            std::unique_ptr<Dataset>& out)
+{
+    if (!x || !y || !t) return fail(HAWKES_EINVAL, "event pointer is NULL");
+    if (n < 1) return fail(HAWKES_EINVAL, "n = %lld < 1", (long long)n);
+    if (n > (int64_t)1 << 30) return fail(HAWKES_EINVAL, "n = %lld exceeds 2^30", (long long)n);
+    for (int64_t k = 0; k < n; ++k) {
+        if (!std::isfinite(x[k]) || !std::isfinite(y[k]) || !std::isfinite(t[k]))
+            return fail(HAWKES_EINVAL, "event %lld has a non-finite coordinate", (long long)k);
+        if (t[k] < 0.0) return fail(HAWKES_EINVAL, "event %lld has t = %g < 0", (long long)k, t[k]);
+        if (std::fabs(x[k]) > 1e15 || std::fabs(y[k]) > 1e15)
+            return fail(HAWKES_EINVAL, "event %lld has |x| or |y| > 1e15", (long long)k);
+    }
+    auto d = std::make_unique<Dataset>();
+    d->n = n;
+    d->npad = (int)(((n + kPad - 1) / kPad) * kPad);
+    d->perm.resize(n);
+    std::iota(d->perm.begin(), d->perm.end(), 0);
+    std::stable_sort(d->perm.begin(), d->perm.end(), [&](int a, int b) { return t[a] < t[b]; });
+
+    double xmin = x[0], xmax = x[0], ymin = y[0], ymax = y[0], tmin = t[0], tmax = t[0];
+    for (int64_t k = 1; k < n; ++k) {
+        xmin = std::min(xmin, x[k]); xmax = std::max(xmax, x[k]);
+        ymin = std::min(ymin, y[k]); ymax = std::max(ymax, y[k]);
+        tmin = std::min(tmin, t[k]); tmax = std::max(tmax, t[k]);
+    }
+    d->T = tmax;
+    const double cx = 0.5 * (xmin + xmax), cy = 0.5 * (ymin + ymax), ctm = 0.5 * (tmin + tmax);
+
+    const int np = d->npad;
+    std::vector<float4> ev32((size_t)2 * np);
+    std::vector<double4> ev64(np);
+    std::vector<int> cut(np);
+    auto split = [](double v, float& hi, float& lo) {
+        hi = (float)v;
+        lo = (float)(v - (double)hi);
+    };
+    int run_start = 0;
+    for (int k = 0; k < np; ++k) {
+        if (k < n) {
+            const int src = d->perm[k];
+            float xh, xl, yh, yl, th, tl;
+            split(x[src] - cx, xh, xl);
+            split(y[src] - cy, yh, yl);
+            split(t[src] - ctm, th, tl);
+            ev32[2 * k] = make_float4(xh, yh, th, 0.0f);
+            ev32[2 * k + 1] = make_float4(xl, yl, tl, 0.0f);
+            ev64[k] = make_double4(x[src], y[src], t[src], 0.0);
+            if (k > 0 && t[src] != t[d->perm[k - 1]]) run_start = k;
+            cut[k] = run_start;  // events before the first one with this time are exactly the earlier ones
+        } else {
+            ev32[2 * k] = make_float4((float)kSentinel, (float)kSentinel, 0.0f, 0.0f);
+            ev32[2 * k + 1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            ev64[k] = make_double4(kSentinel, kSentinel, 0.0, 0.0);
+            cut[k] = (int)n;
+        }
+    }
+    const size_t b32 = ev32.size() * sizeof(float4), b64 = ev64.size() * sizeof(double4), bc = cut.size() * sizeof(int);
+    void *p32 = nullptr, *p64 = nullptr, *pc = nullptr;
+    hawkes_status st;
+    if ((st = dev_alloc(c, &p32, b32)) != HAWKES_OK) return st;
+    if ((st = dev_alloc(c, &p64, b64)) != HAWKES_OK) {
+        dev_free(c, p32, b32);
+        return st;
+    }
+    if ((st = dev_alloc(c, &pc, bc)) != HAWKES_OK) {
+        dev_free(c, p32, b32);
+        dev_free(c, p64, b64);
+        return st;
+    }
+    d->ev32 = (float4*)p32;
+    d->ev64 = (double4*)p64;
+    d->cut = (int*)pc;
+    d->bytes = b32 + b64 + bc;
+    hipError_t e = hipMemcpy(p32, ev32.data(), b32, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(p64, ev64.data(), b64, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(pc, cut.data(), bc, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_dataset(c, *d);
+        return hip_fail(e, "hipMemcpy (dataset upload)");
+    }
+    out = std::move(d);
+    return HAWKES_OK;
+}
+
+void free_dataset(hawkes_ctx* c, Dataset& d)
+{
+    dev_free(c, d.ev32, (size_t)2 * d.npad * sizeof(float4));
+    dev_free(c, d.ev64, (size_t)d.npad * sizeof(double4));
+    dev_free(c, d.cut, (size_t)d.npad * sizeof(int));
+    d.ev32 = nullptr;
+    d.ev64 = nullptr;
+    d.cut = nullptr;
+}
+
+}  // namespace hawkes
+
+using namespace hawkes;
+
+extern "C" {
+
+const char* hawkes_last_error(void) { return g_last_error.c_str(); }
+
+hawkes_status hawkes_create(int device, size_t hbm_budget_bytes, void* hip_stream, hawkes_ctx** out)
+{
+    if (!out) return fail(HAWKES_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev) return fail(HAWKES_EINVAL, "device %d not in [0, %d)", device, ndev);
+    if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+    auto c = std::make_unique<hawkes_ctx>();
+    c->device = device;
+    size_t free_b = 0, total_b = 0;
+    if ((e = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) return hip_fail(e, "hipMemGetInfo");
+    c->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.9 * (double)free_b);
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+        c->own_stream = false;
+    } else {
+        if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(e, "hipStreamCreate");
+        c->own_stream = true;
+    }
+    if ((e = hipEventCreateWithFlags(&c->blk_free, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&c->prof_ev[0])) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipEventCreate(&c->prof_ev[1])) != hipSuccess) return hip_fail(e, "hipEventCreate");
+    if ((e = hipHostMalloc((void**)&c->h_out7, 8 * sizeof(double), hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "hipHostMalloc");
+    hawkes_status st = server_start(c.get());
+    if (st != HAWKES_OK) return st;
+    *out = c.release();
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_destroy(hawkes_ctx* c)
+{
+    if (!c) return HAWKES_OK;
+    (void)hipSetDevice(c->device);
+    server_stop(c);
+    (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        for (auto& kv : c->datasets) free_dataset(c, *kv.second);
+        c->datasets.clear();
+        c->blk.release(c);
+    }
+    if (c->h_out7) (void)hipHostFree(c->h_out7);
+    (void)hipEventDestroy(c->blk_free);
+    (void)hipEventDestroy(c->prof_ev[0]);
+    (void)hipEventDestroy(c->prof_ev[1]);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_dataset_create(hawkes_ctx* c, const double* x, const double* y, const double* t, int64_t n,
+                                    int32_t* out_id)
+{
+    hawkes_status st = begin_call(c);
+    if (st != HAWKES_OK) return st;
+    if (!out_id) return fail(HAWKES_EINVAL, "out_id is NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    std::unique_ptr<Dataset> d;
+    if ((st = build_dataset(c, x, y, t, n, d)) != HAWKES_OK) return poison(c, st);
+    d->id = c->next_id++;
+    *out_id = d->id;
+    c->datasets[d->id] = std::move(d);
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_dataset_destroy(hawkes_ctx* c, int32_t id)
+{
+    hawkes_status st = begin_call(c);
+    if (st != HAWKES_OK) return st;
+    std::lock_guard<std::mutex> lk(c->mu);
+    Dataset* d = find_dataset(c, id);
+    if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
+    if (d->inflight > 0) return fail(HAWKES_EBUSY, "dataset %d has %d requests in flight", id, d->inflight);
+    // Blocking and device calls may still read it on the device.
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return poison(c, hip_fail(e, "hipDeviceSynchronize"));
+    free_dataset(c, *d);
+    c->datasets.erase(id);
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_dataset_info(hawkes_ctx* c, int32_t id, int64_t* n, size_t* device_bytes)
+{
+    if (!c) return fail(HAWKES_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    Dataset* d = find_dataset(c, id);
+    if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
+    if (n) *n = d->n;
+    if (device_bytes) *device_bytes = d->bytes;
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_loglik(hawkes_ctx* c, int32_t id, const hawkes_params* p, int precision, double* out_loglik)
+{
+    if (!out_loglik) return fail(HAWKES_EINVAL, "out_loglik is NULL");
+    double o[7];
+    hawkes_status st = blocking_eval(c, id, p, precision, false, o, nullptr);
+    if (st == HAWKES_OK) *out_loglik = o[0];
+    return st;
+}
+
+hawkes_status hawkes_grad(hawkes_ctx* c, int32_t id, const hawkes_params* p, int precision, double* out_loglik,
+                          double* out_grad)
+{
+    if (!out_loglik || !out_grad) return fail(HAWKES_EINVAL, "output pointer is NULL");
+    double o[7];
+    hawkes_status st = blocking_eval(c, id, p, precision, true, o, nullptr);
+    if (st == HAWKES_OK) {
+        *out_loglik = o[0];
+        memcpy(out_grad, o + 1, 6 * sizeof(double));
+    }
+    return st;
+}
+
+hawkes_status hawkes_rows(hawkes_ctx* c, int32_t id, const hawkes_params* p, int precision, double* out_rows)
+{
+    if (!out_rows) return fail(HAWKES_EINVAL, "out_rows is NULL");
+    double o[7];
+    return blocking_eval(c, id, p, precision, true, o, out_rows);
+}
+
+hawkes_status hawkes_grad_device(hawkes_ctx* c, int32_t id, const hawkes_params* p, int precision, double* d_out7,
+                                 void* hip_stream)
+{
+    hawkes_status st = begin_call(c);
+    if (st != HAWKES_OK) return st;
+    if (!d_out7) return fail(HAWKES_EINVAL, "d_out7 is NULL");
+    if ((st = check_params(p)) != HAWKES_OK) return st;
+    if (precision != HAWKES_FP64 && precision != HAWKES_FP32C)
+        return fail(HAWKES_EINVAL, "precision %d is neither HAWKES_FP64 nor HAWKES_FP32C", precision);
+    std::lock_guard<std::mutex> lk(c->mu);
+    Dataset* d = find_dataset(c, id);
+    if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
+    const Plan pl = make_plan(d->n, d->npad, true);
+    if ((st = c->blk.reserve(c, scratch_bytes(pl, d->n, false))) != HAWKES_OK) return st;
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    // The scratch is shared with every other blocking or device call of this context.
+    hipError_t e = hipStreamWaitEvent(s, c->blk_free, 0);
+    if (e != hipSuccess) return poison(c, hip_fail(e, "hipStreamWaitEvent"));
+    st = enqueue_eval(c, *d, *p, precision, true, c->blk.base, d_out7, nullptr, nullptr, false, s);
+    if (st != HAWKES_OK) return poison(c, st);
+    e = hipEventRecord(c->blk_free, s);
+    if (e != hipSuccess) return poison(c, hip_fail(e, "hipEventRecord"));
+    c->prof_pending = false;  // not waited for here; device calls are not profiled
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_profile(hawkes_ctx* c, int enable)
+{
+    if (!c) return fail(HAWKES_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->profile = enable != 0;
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_kernel_time(hawkes_ctx* c, double* pair_ms, int64_t* pair_launches, int reset)
+{
+    if (!c) return fail(HAWKES_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    if (pair_ms) *pair_ms = c->pair_ms;
+    if (pair_launches) *pair_launches = c->pair_launches;
+    if (reset) {
+        c->pair_ms = 0.0;
+        c->pair_launches = 0;
+    }
+    return HAWKES_OK;
+}
+
+}  // extern "C"

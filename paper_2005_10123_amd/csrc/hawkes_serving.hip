@@ -1,0 +1,407 @@
+// hawkes_serving.hip -- continuous batching of likelihood / gradient requests (hawkes_submit /
+// hawkes_poll).
+//
+// Many samplers each ask for one evaluation per proposal (the likelihood step of the paper's
+// Algorithm 1).  A scheduler thread per context:
+//   * admits queued requests in arrival order while launch slots and the HBM budget allow; each
+//     admitted request gets a scratch buffer from a pool (its partial sums and block partials);
+//   * packs admitted requests of one kind (precision, with/without gradient) into one launch of
+//     the three evaluation kernels -- the work items of all requests in a launch share the grid;
+//   * issues each launch on the next of several streams, so a launch built from requests that
+//     arrived while earlier ones were running overlaps them on the device;
+//   * reaps finished launches by event query, returns the scratch to the pool and publishes the
+//     results for hawkes_poll.
+// Every request is evaluated with the plan of its own (n, gradient) and its own scratch, so its
+// result is bitwise the same alone, blocking or in any mix.
+#include "hawkes_runtime.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+
+namespace hawkes {
+
+namespace {
+
+constexpr int kStreams = 3;
+constexpr int kMaxLaunches = 8;
+constexpr int kMaxAdmitted = 64;
+
+uint64_t now_ns()
+{
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+struct Pending {
+    hawkes_request req;
+    uint64_t t_submit;
+};
+
+struct PoolBuf {
+    Scratch s;
+    bool busy = false;
+};
+
+struct Launch {
+    bool busy = false;
+    bool failed = false;  // an enqueue step failed: complete every request with HAWKES_EDEVICE
+    hipEvent_t done = nullptr;
+    double* d_out = nullptr;  // kMaxBatch x 8 doubles
+    double* h_out = nullptr;  // pinned mirror
+    int nreq = 0;
+    Pending req[kMaxBatch];
+    int buf[kMaxBatch];
+};
+
+}  // namespace
+
+struct Server {
+    std::mutex mu;  // pending, done, outstanding, stop
+    std::condition_variable cv_work, cv_done;
+    std::deque<Pending> pending;
+    std::deque<hawkes_result> done;
+    int64_t outstanding = 0;
+    bool stop = false;
+    std::thread th;
+    hipStream_t streams[kStreams] = {};
+    int next_stream = 0;
+    // Scheduler-thread state (pool buffers are allocated under the context lock).
+    std::vector<PoolBuf> pool;
+    Launch launches[kMaxLaunches];
+    int admitted = 0;
+};
+
+namespace {
+
+hawkes_result make_result(const Pending& p, hawkes_status st)
+{
+    hawkes_result r;
+    memset(&r, 0, sizeof r);
+    r.tag = p.req.tag;
+    r.status = st;
+    r.t_submit_ns = p.t_submit;
+    r.t_done_ns = now_ns();
+    return r;
+}
+
+void publish(Server* sv, const hawkes_result* r, int n)
+{
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (int k = 0; k < n; ++k) sv->done.push_back(r[k]);
+    sv->cv_done.notify_all();
+}
+
+// Pool buffer of at least `need` bytes, or -1 if the budget cannot provide one right now.
+// Caller holds c->mu.
+int get_buffer(hawkes_ctx* c, Server* sv, size_t need)
+{
+    int best = -1;
+    for (int k = 0; k < (int)sv->pool.size(); ++k) {
+        const PoolBuf& b = sv->pool[k];
+        if (!b.busy && b.s.bytes >= need && (best < 0 || b.s.bytes < sv->pool[best].s.bytes)) best = k;
+    }
+    if (best >= 0) return best;
+    const size_t round = (size_t)1 << 20;
+    const size_t want = (need + round - 1) / round * round;
+    if (c->used + want > c->budget) {
+        // Give back idle buffers (too small for this request) before giving up.  Entries stay in
+        // the pool so the indices held by running launches remain valid.
+        for (auto& b : sv->pool)
+            if (!b.busy && b.s.base) b.s.release(c);
+        if (c->used + want > c->budget) return -1;
+    }
+    int slot = -1;
+    for (int k = 0; k < (int)sv->pool.size(); ++k)
+        if (!sv->pool[k].busy && !sv->pool[k].s.base) slot = k;
+    if (slot < 0) {
+        sv->pool.push_back(PoolBuf());
+        slot = (int)sv->pool.size() - 1;
+    }
+    if (sv->pool[slot].s.reserve(c, want) != HAWKES_OK) return -1;
+    return slot;
+}
+
+void reap(hawkes_ctx* c, Server* sv)
+{
+    for (auto& L : sv->launches) {
+        if (!L.busy) continue;
+        hipError_t e = L.failed ? hipSuccess : hipEventQuery(L.done);
+        if (e == hipErrorNotReady) continue;
+        hawkes_result res[kMaxBatch];
+        const hawkes_status st = (e == hipSuccess && !L.failed) ? HAWKES_OK : HAWKES_EDEVICE;
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            for (int k = 0; k < L.nreq; ++k) {
+                res[k] = make_result(L.req[k], st);
+                if (st == HAWKES_OK) {
+                    res[k].loglik = L.h_out[8 * k];
+                    for (int p = 0; p < 6; ++p) res[k].grad[p] = L.h_out[8 * k + 1 + p];
+                }
+                sv->pool[L.buf[k]].busy = false;
+                if (Dataset* d = find_dataset(c, L.req[k].req.dataset)) d->inflight -= 1;
+            }
+            if (st != HAWKES_OK) c->poisoned = true;
+        }
+        sv->admitted -= L.nreq;
+        L.busy = false;
+        publish(sv, res, L.nreq);
+    }
+}
+
+int free_launch(Server* sv)
+{
+    for (int k = 0; k < kMaxLaunches; ++k)
+        if (!sv->launches[k].busy) return k;
+    return -1;
+}
+
+bool any_busy(Server* sv)
+{
+    for (auto& L : sv->launches)
+        if (L.busy) return true;
+    return false;
+}
+
+// Admit and launch as much queued work as slots and budget allow.
+void admit(hawkes_ctx* c, Server* sv)
+{
+    while (true) {
+        const int li = free_launch(sv);
+        if (li < 0 || sv->admitted >= kMaxAdmitted) return;
+        Launch& L = sv->launches[li];
+        std::vector<Pending> cand;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (sv->pending.empty()) return;
+            // The head request decides the kind of this launch; later requests of the same kind
+            // join it (up to kMaxBatch); requests of other kinds keep their place in the queue.
+            const int prec = sv->pending.front().req.precision, grad = sv->pending.front().req.want_grad;
+            for (auto it = sv->pending.begin(); it != sv->pending.end() && (int)cand.size() < kMaxBatch;) {
+                if (it->req.precision == prec && it->req.want_grad == grad &&
+                    sv->admitted + (int)cand.size() < kMaxAdmitted) {
+                    cand.push_back(*it);
+                    it = sv->pending.erase(it);
+                } else {
+                    ++it;
+                }
+            }
+        }
+        PairBatch pb;
+        EpiBatch eb;
+        memset(&pb, 0, sizeof pb);
+        memset(&eb, 0, sizeof eb);
+        int nb = 0, items = 0, epi_items = 0;
+        std::vector<Pending> back;  // could not get memory now: return to the queue front
+        std::vector<hawkes_result> failed;
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            for (size_t k = 0; k < cand.size(); ++k) {
+                const Pending& p = cand[k];
+                Dataset* d = find_dataset(c, p.req.dataset);
+                if (!d) {
+                    failed.push_back(make_result(p, HAWKES_ENOTFOUND));
+                    continue;
+                }
+                const bool grad = p.req.want_grad != 0;
+                const Plan pl = make_plan(d->n, d->npad, grad);
+                const size_t need = scratch_bytes(pl, d->n, false);
+                int bi = back.empty() ? get_buffer(c, sv, need) : -1;
+                if (bi < 0) {
+                    if (!back.empty() || sv->admitted + nb > 0 || any_busy(sv)) {
+                        back.push_back(p);  // wait for memory held by running work
+                    } else {
+                        d->inflight -= 1;
+                        failed.push_back(make_result(p, HAWKES_ENOMEM));
+                    }
+                    continue;
+                }
+                sv->pool[bi].busy = true;
+                double *part, *bp, *o7, *rows;
+                carve(sv->pool[bi].s.base, pl, d->n, false, &part, &bp, &o7, &rows);
+                fill_pair(p.req.p, *d, pl, pb.r[nb]);
+                pb.r[nb].part = part;
+                pb.r[nb].item_begin = items;
+                items += pl.row_blocks * pl.splits;
+                fill_epi(p.req.p, *d, pl, grad, eb.r[nb]);
+                eb.r[nb].part = part;
+                eb.r[nb].block_part = bp;
+                eb.r[nb].out7 = L.d_out + 8 * nb;
+                eb.r[nb].rows_out = nullptr;
+                eb.r[nb].item_begin = epi_items;
+                epi_items += pl.epi_blocks;
+                L.req[nb] = p;
+                L.buf[nb] = bi;
+                ++nb;
+            }
+        }
+        if (!failed.empty()) publish(sv, failed.data(), (int)failed.size());
+        if (!back.empty()) {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            for (auto it = back.rbegin(); it != back.rend(); ++it) sv->pending.push_front(*it);
+        }
+        if (nb == 0) return;
+        pb.nreq = eb.nreq = nb;
+        pb.total_items = items;
+        eb.total_items = epi_items;
+        hipStream_t s = sv->streams[sv->next_stream];
+        sv->next_stream = (sv->next_stream + 1) % kStreams;
+        const int prec = L.req[0].req.precision;
+        const bool grad = L.req[0].req.want_grad != 0;
+        hipError_t e = launch_pair(pb, prec, grad, s);
+        if (e == hipSuccess) e = launch_epilogue(eb, s);
+        if (e == hipSuccess) e = launch_final(eb, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(L.h_out, L.d_out, (size_t)nb * 8 * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipEventRecord(L.done, s);
+        L.nreq = nb;
+        sv->admitted += nb;
+        L.busy = true;
+        L.failed = e != hipSuccess;  // reaped as a device failure on the next pass
+        if (L.failed) {
+            // Let the device finish whatever was enqueued before the scratch is reused.
+            (void)hipStreamSynchronize(s);
+        }
+        if (!back.empty()) return;
+    }
+}
+
+void scheduler(hawkes_ctx* c)
+{
+    Server* sv = c->server;
+    (void)hipSetDevice(c->device);
+    while (true) {
+        reap(c, sv);
+        admit(c, sv);
+        std::unique_lock<std::mutex> lk(sv->mu);
+        if (sv->stop) break;
+        if (any_busy(sv)) {
+            // Launches in flight: look again soon (completion is observed by event query).
+            sv->cv_work.wait_for(lk, std::chrono::microseconds(20));
+        } else {
+            sv->cv_work.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
+        }
+        if (sv->stop) break;
+    }
+}
+
+}  // namespace
+
+hawkes_status server_start(hawkes_ctx* c)
+{
+    auto sv = std::make_unique<Server>();
+    hipError_t e;
+    for (auto& s : sv->streams)
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return hip_fail(e, "hipStreamCreate");
+    for (auto& L : sv->launches) {
+        if ((e = hipEventCreateWithFlags(&L.done, hipEventDisableTiming)) != hipSuccess) return hip_fail(e, "hipEventCreate");
+        if ((e = hipMalloc((void**)&L.d_out, kMaxBatch * 8 * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = hipHostMalloc((void**)&L.h_out, kMaxBatch * 8 * sizeof(double), hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "hipHostMalloc");
+    }
+    c->server = sv.release();
+    c->server->th = std::thread(scheduler, c);
+    return HAWKES_OK;
+}
+
+void server_stop(hawkes_ctx* c)
+{
+    Server* sv = c->server;
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop = true;
+        sv->cv_work.notify_all();
+        sv->cv_done.notify_all();
+    }
+    if (sv->th.joinable()) sv->th.join();
+    (void)hipDeviceSynchronize();
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        for (auto& b : sv->pool) b.s.release(c);
+    }
+    for (auto& L : sv->launches) {
+        (void)hipEventDestroy(L.done);
+        (void)hipFree(L.d_out);
+        (void)hipHostFree(L.h_out);
+    }
+    for (auto& s : sv->streams) (void)hipStreamDestroy(s);
+    c->server = nullptr;
+    delete sv;
+}
+
+}  // namespace hawkes
+
+using namespace hawkes;
+
+extern "C" {
+
+hawkes_status hawkes_submit(hawkes_ctx* c, const hawkes_request* reqs, int32_t n)
+{
+    if (!c) return fail(HAWKES_EINVAL, "ctx is NULL");
+    if (n < 0 || (n > 0 && !reqs)) return fail(HAWKES_EINVAL, "bad request array");
+    if (c->poisoned) return fail(HAWKES_EDEVICE, "context is unusable after an earlier device failure");
+    Server* sv = c->server;
+    const uint64_t t = now_ns();
+    std::vector<Pending> ok;
+    std::vector<hawkes_result> bad;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        for (int k = 0; k < n; ++k) {
+            Pending p{reqs[k], t};
+            hawkes_status st = check_params(&reqs[k].p);
+            if (st == HAWKES_OK && reqs[k].precision != HAWKES_FP64 && reqs[k].precision != HAWKES_FP32C)
+                st = HAWKES_EINVAL;
+            if (st == HAWKES_OK && reqs[k].want_grad != 0 && reqs[k].want_grad != 1) st = HAWKES_EINVAL;
+            Dataset* d = st == HAWKES_OK ? find_dataset(c, reqs[k].dataset) : nullptr;
+            if (st == HAWKES_OK && !d) st = HAWKES_ENOTFOUND;
+            if (st != HAWKES_OK) {
+                bad.push_back(make_result(p, st));
+                continue;
+            }
+            d->inflight += 1;
+            ok.push_back(p);
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (auto& p : ok) sv->pending.push_back(p);
+        for (auto& r : bad) sv->done.push_back(r);
+        sv->outstanding += n;
+        sv->cv_work.notify_all();
+        if (!bad.empty()) sv->cv_done.notify_all();
+    }
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_poll(hawkes_ctx* c, hawkes_result* out, int32_t cap, int32_t* n_out, int64_t timeout_us)
+{
+    if (!c || !n_out || cap < 0 || (cap > 0 && !out)) return fail(HAWKES_EINVAL, "bad poll arguments");
+    *n_out = 0;
+    Server* sv = c->server;
+    std::unique_lock<std::mutex> lk(sv->mu);
+    auto ready = [&] { return !sv->done.empty() || sv->stop; };
+    if (timeout_us > 0)
+        sv->cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), ready);
+    else if (timeout_us < 0)
+        sv->cv_done.wait(lk, [&] { return ready() || sv->outstanding == 0; });
+    int32_t k = 0;
+    while (k < cap && !sv->done.empty()) {
+        out[k++] = sv->done.front();
+        sv->done.pop_front();
+    }
+    sv->outstanding -= k;
+    *n_out = k;
+    if (k == 0) return fail(HAWKES_EAGAIN, "no completed request");
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_outstanding(hawkes_ctx* c, int64_t* n)
+{
+    if (!c || !n) return fail(HAWKES_EINVAL, "bad arguments");
+    std::lock_guard<std::mutex> lk(c->server->mu);
+    *n = c->server->outstanding;
+    return HAWKES_OK;
+}
+
+}  // extern "C"

@@ -11,3 +11,26 @@ if HERE not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library through its C ABI)")
+
+
+def _has_gpu():
+    try:
+        import torch
+
+        return torch.cuda.is_available()
+    except Exception:
+        return False
+
+
+def pytest_collection_modifyitems(config, items):
+    """Without a GPU, skip the gpu-marked tests unless they were asked for explicitly with -m gpu
+    (then they run and fail loudly: the product has no CPU fallback)."""
+    expr = (config.option.markexpr or "").replace(" ", "")
+    if expr == "gpu" or _has_gpu():
+        return
+    import pytest
+
+    skip = pytest.mark.skip(reason="no GPU in this environment")
+    for item in items:
+        if "gpu" in item.keywords:
+            item.add_marker(skip)

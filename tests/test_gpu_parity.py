@@ -1,0 +1,176 @@
+"""HIP path (through the C ABI) against the FP64 oracle: small fixtures, ragged sizes spanning
+several tiles, ties and degenerate inputs, per-event outputs, the 2,000-event workload in full and
+the 85,000-event workloads on sampled rows plus size-independent properties."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import TOL, assert_close, grad_errors, rel, row_ell_error
+from paper_2005_10123_amd import binding, synth
+import oracle_pins as P
+
+pytestmark = pytest.mark.gpu
+PRECS = ["fp64", "fp32c"]
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = binding.Context(0)
+    yield c
+    c.close()
+
+
+def check_full(ctx, x, y, t, th, what, precs=PRECS):
+    ref = oracle.evaluate(x, y, t, th, rows=True)
+    ds = ctx.dataset(x, y, t)
+    try:
+        for prec in precs:
+            ell, g = ctx.grad(ds, th, prec)
+            assert_close(ell, g, ref, prec, what, th)
+            ell2 = ctx.loglik(ds, th, prec)
+            assert rel(ell2, ref["ell"]) <= TOL[prec], (what, prec, "loglik-only", ell2, ref["ell"])
+    finally:
+        ds.close()
+    return ref
+
+
+@pytest.mark.parametrize("case", ["E1_single", "E2_pair", "E3_tie", "E4_five", "E5_unsorted"])
+@pytest.mark.parametrize("thn", ["theta_small", "theta_posterior_regime"])
+def test_small_fixtures(ctx, case, thn):
+    x, y, t = P._case(case)
+    check_full(ctx, x, y, t, P._theta(thn), case)
+
+
+@pytest.mark.parametrize("n", [2, 3, 63, 64, 65, 255, 256, 257, 1023, 1024, 1025, 2049, 4097])
+def test_ragged_sizes(ctx, n):
+    x, y, t = synth.simulate(synth.SimSpec(n, 4.0, 200.0, 3, 0.5, 0.1, 0.4, (7, n, 1)))
+    perm = np.random.default_rng(n).permutation(n)  # the library must not depend on input order
+    check_full(ctx, x[perm], y[perm], t[perm], (1.0, 0.5, 20.0, 0.4, 0.5, 0.1), f"n={n}")
+
+
+def test_small_workload_full(ctx):
+    (x, y, t), th = synth.config_events("small_2k")
+    check_full(ctx, x, y, t, th, "small_2k")
+
+
+def test_ties_and_degenerate(ctx):
+    rng = np.random.default_rng(5)
+    n = 700
+    x, y = rng.uniform(0, 1, n), rng.uniform(0, 1, n)
+    t = np.round(rng.uniform(0, 30, n))  # many exact ties in time
+    check_full(ctx, x, y, t, (1.0, 0.3, 5.0, 0.5, 0.8, 0.2), "ties")
+    check_full(ctx, x, y, np.full(n, 7.0), (1.0, 0.3, 5.0, 0.5, 0.8, 0.2), "all one time")
+    check_full(ctx, np.full(300, 2.0), np.full(300, -1.0), np.full(300, 3.0), (1, 0.5, 20, 0.3, 0.5, 0.1),
+               "identical events")
+    check_full(ctx, x, y, t, (1.0, 0.3, 5.0, 0.0, 0.8, 0.2), "theta=0")
+
+
+def test_per_event_rows(ctx):
+    x, y, t = synth.simulate(synth.SimSpec(1500, 5.0, 300.0, 3, 0.5, 0.1, 0.5, (9, 9, 9)))
+    perm = np.random.default_rng(1).permutation(x.size)
+    x, y, t = x[perm], y[perm], t[perm]
+    th = (1.2, 0.4, 15.0, 0.5, 0.5, 0.1)
+    ref = oracle.evaluate(x, y, t, th, rows=True)
+    ds = ctx.dataset(x, y, t)
+    for prec in PRECS:
+        r = ctx.rows(ds, th, prec)
+        tol = TOL[prec]
+        assert row_ell_error(r["ell"], ref["row_ell"]) <= tol
+        assert np.max(np.abs(r["lambda"] - np.exp(ref["row_ell"] + ref["row_Lambda"])) / r["lambda"]) <= 10 * tol
+        assert np.max(np.abs(r["Lambda"] - ref["row_Lambda"]) / np.abs(ref["row_Lambda"])) <= tol
+        assert np.max(np.abs(r["pi"] - ref["row_pi"])) <= tol
+        scale = np.abs(ref["row_grad"]).max(axis=0)
+        assert np.max(np.abs(r["grad"] - ref["row_grad"]) / scale) <= tol
+    ds.close()
+
+
+def test_deterministic_and_translation(ctx):
+    x, y, t = synth.simulate(synth.SimSpec(3000, 8.0, 500.0, 3, 0.5, 0.1, 0.3, (4, 4, 4)))
+    th = (1.0, 0.5, 20.0, 0.3, 0.5, 0.1)
+    ds = ctx.dataset(x, y, t)
+    for prec in PRECS:
+        a = ctx.grad(ds, th, prec)
+        b = ctx.grad(ds, th, prec)
+        assert a[0] == b[0] and np.array_equal(a[1], b[1]), "repeat must be bitwise identical"
+    ds2 = ctx.dataset(x + 1000.0, y - 250.0, t)
+    for prec in PRECS:
+        a = ctx.grad(ds, th, prec)
+        b = ctx.grad(ds2, th, prec)
+        assert rel(b[0], a[0]) <= TOL[prec]
+    ds.close()
+    ds2.close()
+
+
+# ---- full-size workloads (85,000 events): sampled rows and size-independent properties ----------
+@pytest.fixture(scope="module")
+def city(ctx):
+    (x, y, t), th = synth.config_events("city_85k_10km")
+    ds = ctx.dataset(x, y, t)
+    yield x, y, t, th, ds
+    ds.close()
+
+
+def test_city_sampled_rows(ctx, city):
+    x, y, t, th, ds = city
+    n = x.size
+    rng = np.random.default_rng(85)
+    idx = np.unique(np.concatenate([[0, 1, n // 2, n - 2, n - 1], rng.integers(0, n, 60)]))
+    ref = oracle.rows(x, y, t, th, idx)
+    for prec in PRECS:
+        r = ctx.rows(ds, th, prec)
+        tol = TOL[prec]
+        assert row_ell_error(r["ell"][idx], ref["ell"]) <= tol, prec
+        assert np.max(np.abs(r["lambda"][idx] - ref["lambda"]) / ref["lambda"]) <= tol, prec
+        assert np.max(np.abs(r["pi"][idx] - ref["pi"])) <= tol, prec
+        scale = np.abs(ref["grad"]).max(axis=0)
+        assert np.max(np.abs(r["grad"][idx] - ref["grad"]) / scale) <= tol, prec
+        # mu0 dl/dmu0 + theta dl/dtheta = N - Lambda, from the same pass at full size
+        ell, g = ctx.grad(ds, th, prec)
+        lhs = th[0] * g[0] + th[3] * g[3]
+        rhs = n - r["Lambda"].sum()
+        assert abs(lhs - rhs) <= tol * np.abs(r["grad"][:, [0, 3]]).sum() + 1e-9 * n, (prec, lhs, rhs)
+        assert abs(ell - r["ell"].sum()) <= 1e-9 * np.abs(r["ell"]).sum()
+
+
+def test_city_fp32c_vs_fp64(ctx, city):
+    x, y, t, th, ds = city
+    e64, g64 = ctx.grad(ds, th, "fp64")
+    e32, g32 = ctx.grad(ds, th, "fp32c")
+    rows64 = ctx.rows(ds, th, "fp64")
+    assert rel(e32, e64) <= TOL["fp32c"]
+    plain, normed = grad_errors(g32, g64, rows64["grad"], e64, th)
+    assert np.all(normed <= TOL["fp32c"]), normed
+
+
+def test_city_finite_differences(ctx, city):
+    """Central differences (step 1e-6 relative) of the FP64 GPU log-likelihood vs both gradients."""
+    x, y, t, th, ds = city
+    th = np.array(th)
+    rows = ctx.rows(ds, th, "fp64")
+    l1 = np.abs(rows["grad"]).sum(axis=0)
+    _, g64 = ctx.grad(ds, th, "fp64")
+    _, g32 = ctx.grad(ds, th, "fp32c")
+    for p in range(6):
+        step = 1e-6 * th[p]
+        tp, tm = th.copy(), th.copy()
+        tp[p] += step
+        tm[p] -= step
+        fd = (ctx.loglik(ds, tp, "fp64") - ctx.loglik(ds, tm, "fp64")) / (2 * step)
+        assert abs(fd - g64[p]) <= 1e-6 * l1[p], (p, fd, g64[p])
+        assert abs(fd - g32[p]) <= 1e-5 * l1[p], (p, fd, g32[p])
+
+
+def test_loglik_workload_sampled(ctx):
+    (x, y, t), th = synth.config_events("city_85k_15km")
+    ds = ctx.dataset(x, y, t)
+    n = x.size
+    idx = np.unique(np.random.default_rng(2).integers(0, n, 50))
+    ref = oracle.rows(x, y, t, th, idx)
+    for prec in PRECS:
+        r = ctx.rows(ds, th, prec)
+        assert row_ell_error(r["ell"][idx], ref["ell"]) <= TOL[prec], prec
+        assert np.max(np.abs(r["lambda"][idx] - ref["lambda"]) / ref["lambda"]) <= TOL[prec], prec
+    e64 = ctx.loglik(ds, th, "fp64")
+    e32 = ctx.loglik(ds, th, "fp32c")
+    assert rel(e32, e64) <= TOL["fp32c"]
+    ds.close()
