@@ -38,8 +38,10 @@ struct PairReq {
     int splits;           // column ranges the j loop is cut into
     int tiles_per_split;  // kTile-event tiles in each column range
     int item_begin;       // first work item (block) of this request in the launch
-    // Negated base-2 exponent coefficients: B = 2^(nab r^2 + nbb dt^2), E = 2^(nae r^2 + nbe dt)
-    float nab, nbb, nae, nbe;
+    // Negated base-2 exponent coefficients: B = 2^(nab r^2 + nbb dt^2), E = 2^(nae r^2 + nbe dt).
+    // The FP32C pass works in scaled time dt' = ts dt with ts = tsh + tsl = sqrt(-nbb):
+    // B = 2^(nab r^2 - dt'^2), E = 2^(nae r^2 + kte dt') with kte = nbe / ts.
+    float nab, nae, tsh, tsl, kte;
     double nab64, nbb64, nae64, nbe64;
 };
 
@@ -61,6 +63,7 @@ struct EpiReq {
     double T;             // largest event time
     double mu0, tau_x, tau_t, theta, omega, h;
     double cb, ce;        // background and trigger coefficients
+    double t_scale;       // time scale of the dt-moments in the partial sums (1 for FP64)
 };
 
 struct EpiBatch {

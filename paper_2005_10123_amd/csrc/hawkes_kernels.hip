@@ -31,7 +31,7 @@
 namespace hawkes {
 namespace {
 
-constexpr int kChunk = 32;  // pair terms summed plainly in binary32 before a compensated merge
+constexpr int kChunk = 64;  // pair terms summed plainly in binary32 before a compensated merge
 
 enum Mode : int { kNone = 0, kFull = 1, kMask = 2 };
 
@@ -90,34 +90,46 @@ __device__ __forceinline__ int find_request(const Req* r, int nreq, int item)
 
 // ------------------------------------------------------------------------------------------------
 // FP32C pairwise pass.
+//
+// Each lane holds kRowsPerLane consecutive rows.  Space: dx = (x_i,hi - x_j,hi) + (x_i,lo - x_j,lo)
+// gives the difference to binary32 precision of the difference itself.  Time: every lane measures
+// times from its own first row t0 = t0_hi + t0_lo and scales them by s = sqrt(-nbb), so a column's
+// time tj = s ((tj_hi - t0_hi) + (tj_lo - t0_lo)) is formed once per column per lane and shared by
+// the lane's rows, and dt = ti - tj costs one subtraction per pair.  Its error is of order
+// 2^-24 (|dt| + s |t_row - t0|), with the lane's rows only a few events apart.  The scale turns
+// the background exponent into nab r^2 - dt^2; the epilogue divides the dt-moments by s and s^2.
+// s is applied as s_hi + s_lo: a binary32 s alone would perturb every background exponent by the
+// same relative amount (up to 2^-23), a bias that does not average out over the sum.
 template <int MODE, bool GRAD>
 __device__ __forceinline__ void chunk_fp32(const float4* __restrict__ sj, int jbase,
                                            const float (&xh)[kRowsPerLane], const float (&yh)[kRowsPerLane],
-                                           const float (&th)[kRowsPerLane], const float (&xl)[kRowsPerLane],
-                                           const float (&yl)[kRowsPerLane], const float (&tl)[kRowsPerLane],
-                                           const int (&ct)[kRowsPerLane], float nab, float nbb,
-                                           float nae, float nbe, float (&p)[6][kRowsPerLane])
+                                           const float (&xl)[kRowsPerLane], const float (&yl)[kRowsPerLane],
+                                           const float (&ti)[kRowsPerLane], const int (&ct)[kRowsPerLane],
+                                           float t0h, float t0l, float tsh, float tsl, float nab, float nae, float kte,
+                                           float (&p)[6][kRowsPerLane])
 {
     constexpr int R = kRowsPerLane;
 #pragma unroll 2
     for (int jj = 0; jj < kChunk; ++jj) {
         const float4 hi = sj[2 * jj];
         const float4 lo = sj[2 * jj + 1];
+        const float tu = (hi.z - t0h) + (lo.z - t0l);
+        const float tj = fmaf(tu, tsh, tu * tsl);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const float dx = (xh[r] - hi.x) + (xl[r] - lo.x);
             const float dy = (yh[r] - hi.y) + (yl[r] - lo.y);
-            const float dt = (th[r] - hi.z) + (tl[r] - lo.z);
+            const float dt = ti[r] - tj;
             const float r2 = fmaf(dx, dx, dy * dy);
             const float dt2 = dt * dt;
-            const float b = __builtin_amdgcn_exp2f(fmaf(r2, nab, dt2 * nbb));
+            const float b = __builtin_amdgcn_exp2f(fmaf(r2, nab, -dt2));
             p[0][r] += b;
             if (GRAD) {
                 p[1][r] = fmaf(r2, b, p[1][r]);
                 p[2][r] = fmaf(dt2, b, p[2][r]);
             }
             if (MODE != kNone) {
-                float ae = fmaf(r2, nae, dt * nbe);
+                float ae = fmaf(r2, nae, dt * kte);
                 if (MODE == kMask) ae = (jbase + jj < ct[r]) ? ae : -INFINITY;
                 const float e = __builtin_amdgcn_exp2f(ae);
                 const int ke = GRAD ? 3 : 1;
@@ -147,24 +159,31 @@ __global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
     const int wave = threadIdx.x >> 6;
     const int n = rq.n;
     const int wrow0 = rb * kRowsPerBlock + wave * (64 * R);
-    const bool active = wrow0 < n;  // wave-uniform
+    const int lrow0 = wrow0 + R * lane;  // this lane's rows: lrow0 .. lrow0 + R - 1
+    const bool active = wrow0 < n;       // wave-uniform
 
-    float xh[R], yh[R], th[R], xl[R], yl[R], tl[R];
+    const float tsh = in_vgpr(rq.tsh), tsl = in_vgpr(rq.tsl), nab = in_vgpr(rq.nab);
+    const float nae = in_vgpr(rq.nae), kte = in_vgpr(rq.kte);
+    float xh[R], yh[R], xl[R], yl[R], ti[R];
     int ct[R];
+    float t0h = 0.0f, t0l = 0.0f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const int i = wrow0 + 64 * r + lane;
+        const int i = lrow0 + r;
         const float4 a = rq.ev32[2 * (size_t)i];
         const float4 b = rq.ev32[2 * (size_t)i + 1];
-        xh[r] = a.x; yh[r] = a.y; th[r] = a.z;
-        xl[r] = b.x; yl[r] = b.y; tl[r] = b.z;
+        if (r == 0) {
+            t0h = a.z;
+            t0l = b.z;
+        }
+        xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
+        const float tu = (a.z - t0h) + (b.z - t0l);
+        ti[r] = fmaf(tu, tsh, tu * tsl);
         ct[r] = rq.cut[i];
     }
     // Rows are time-sorted, so the causal counts of the wave's rows lie in [clo, chi].
     const int clo = __builtin_amdgcn_readfirstlane(rq.cut[min(wrow0, n - 1)]);
     const int chi = __builtin_amdgcn_readfirstlane(rq.cut[min(wrow0 + 64 * R - 1, n - 1)]);
-    const float nab = in_vgpr(rq.nab), nbb = in_vgpr(rq.nbb);
-    const float nae = in_vgpr(rq.nae), nbe = in_vgpr(rq.nbe);
 
     float s[K][R], c[K][R];
 #pragma unroll
@@ -192,11 +211,11 @@ __global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
                 for (int r = 0; r < R; ++r) p[k][r] = 0.0f;
             const float4* tj = sj + 2 * ch;
             if (mode == kNone)
-                chunk_fp32<kNone, GRAD>(tj, j0 + ch, xh, yh, th, xl, yl, tl, ct, nab, nbb, nae, nbe, p);
+                chunk_fp32<kNone, GRAD>(tj, j0 + ch, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, p);
             else if (mode == kFull)
-                chunk_fp32<kFull, GRAD>(tj, j0 + ch, xh, yh, th, xl, yl, tl, ct, nab, nbb, nae, nbe, p);
+                chunk_fp32<kFull, GRAD>(tj, j0 + ch, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, p);
             else
-                chunk_fp32<kMask, GRAD>(tj, j0 + ch, xh, yh, th, xl, yl, tl, ct, nab, nbb, nae, nbe, p);
+                chunk_fp32<kMask, GRAD>(tj, j0 + ch, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, p);
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -206,10 +225,8 @@ __global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = wrow0 + 64 * r + lane;
-            rq.part[((size_t)sp * K + k) * rq.npad + i] = (double)s[k][r] + (double)c[k][r];
-        }
+        for (int r = 0; r < R; ++r)
+            rq.part[((size_t)sp * K + k) * rq.npad + lrow0 + r] = (double)s[k][r] + (double)c[k][r];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -359,6 +376,9 @@ __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
                 S[3] += ps[rq.npad];
             }
         }
+        // Moments in dt were summed in scaled time dt' = t_scale dt.
+        S[2] /= rq.t_scale * rq.t_scale;
+        S[4] /= rq.t_scale;
         const double ti = rq.ev64[i].z;
         const double mu0 = rq.mu0, tx = rq.tau_x, tt = rq.tau_t, th = rq.theta, om = rq.omega, h = rq.h;
         const double lam = rq.cb * S[0] + rq.ce * S[3];

@@ -78,7 +78,7 @@ hawkes_status check_params(const hawkes_params* p);
 Plan make_plan(int64_t n, int npad, bool grad);
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows);
 void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, PairReq& r);
-void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, EpiReq& e);
+void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, EpiReq& e);
 void carve(char* base, const Plan& pl, int64_t n, bool rows, double** part, double** block_part, double** out7,
            double** rows_out);
 hawkes_status dev_alloc(hawkes_ctx* c, void** p, size_t bytes);

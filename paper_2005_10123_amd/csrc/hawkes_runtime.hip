@@ -73,12 +73,14 @@ void fold(const hawkes_params& p, PairReq& r)
     r.nae64 = -log2e / (2.0 * p.h * p.h);
     r.nbe64 = -log2e * p.omega;
     r.nab = (float)r.nab64;
-    r.nbb = (float)r.nbb64;
     r.nae = (float)r.nae64;
-    r.nbe = (float)r.nbe64;
+    const double ts = std::sqrt(-r.nbb64);
+    r.tsh = (float)ts;
+    r.tsl = (float)(ts - (double)r.tsh);
+    r.kte = (float)(r.nbe64 / ((double)r.tsh + (double)r.tsl));
 }
 
-void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, EpiReq& e)
+void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, EpiReq& e)
 {
     const double two_pi = 6.28318530717958647693;
     e.ev64 = d.ev64;
@@ -96,6 +98,9 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
     e.h = p.h;
     e.cb = p.mu0 / (std::pow(two_pi, 1.5) * p.tau_x * p.tau_x * p.tau_t);
     e.ce = p.theta * p.omega / (two_pi * p.h * p.h);
+    PairReq folded;
+    fold(p, folded);
+    e.t_scale = precision == kFP32C ? (double)folded.tsh + (double)folded.tsl : 1.0;
 }
 
 void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, PairReq& r)
@@ -196,7 +201,7 @@ hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params&
 
     EpiBatch eb;
     memset(&eb, 0, sizeof eb);
-    fill_epi(p, d, pl, grad, eb.r[0]);
+    fill_epi(p, d, pl, grad, precision, eb.r[0]);
     eb.r[0].part = part;
     eb.r[0].block_part = bp;
     eb.r[0].out7 = out7;

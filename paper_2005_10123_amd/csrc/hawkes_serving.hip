@@ -224,7 +224,7 @@ void admit(hawkes_ctx* c, Server* sv)
                 pb.r[nb].part = part;
                 pb.r[nb].item_begin = items;
                 items += pl.row_blocks * pl.splits;
-                fill_epi(p.req.p, *d, pl, grad, eb.r[nb]);
+                fill_epi(p.req.p, *d, pl, grad, p.req.precision, eb.r[nb]);
                 eb.r[nb].part = part;
                 eb.r[nb].block_part = bp;
                 eb.r[nb].out7 = L.d_out + 8 * nb;
