@@ -8,7 +8,7 @@
 //     (j = i included) and, for causal columns j < cut[i] (t_j < t_i), the unnormalised trigger
 //     E_ij = exp(-omega dt - r^2/(2 h^2)).  With the gradient it also sums r^2 B, dt^2 B, dt E and
 //     r^2 E.  Running sums only, never the N x N terms (the paper's fourth rule of thumb,
-//     Section 3.1).  Layout: a block = 4 waves; each lane keeps kRowsPerLane rows in registers;
+//     Section 2.3).  Layout: a block = 4 waves; each lane keeps kRowsPerLane rows in registers;
 //     the block streams column tiles of kTile events through LDS and every lane reads each column
 //     as a broadcast, so one LDS read feeds 64 x kRowsPerLane pair terms.  The column range is cut
 //     into `splits` pieces so that even one evaluation fills the 256 CUs; each (row block, column

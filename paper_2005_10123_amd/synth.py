@@ -13,7 +13,7 @@ past T_end are dropped; children are not clipped in space.
 
 The mixture layout (K means uniform on [0.2L, 0.8L]^2, sd 0.1L, equal weights) is a reading: the
 paper's data are the Washington D.C. gunfire records, which are not available, and its timing runs
-use unspecified "randomly generated observations" (Section 4.1).  Seeds follow
+use unspecified "randomly generated observations" (Section 3.1).  Seeds follow
 ``numpy.random.PCG64(SeedSequence([10123, config, dataset]))``.
 """
 from __future__ import annotations
