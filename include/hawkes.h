@@ -101,9 +101,11 @@ hawkes_status hawkes_grad(hawkes_ctx* ctx, int32_t id, const hawkes_params* p, i
                           double* out_loglik, double* out_grad);
 
 /* Asynchronous variant of hawkes_grad for callers that own device memory (e.g. a tensor library):
- * enqueues the evaluation on hip_stream (NULL: the context's stream) and writes 7 doubles
- * (ell, then the gradient) to d_out7, device memory of the context's GPU.  Returns once the work
- * is enqueued; the result is valid when that stream reaches this point. */
+ * enqueues the evaluation on hip_stream (a hipStream_t; NULL is the device's null stream, as in
+ * HIP) and writes 7 doubles (ell, then the gradient) to d_out7, device memory of the context's GPU.
+ * Returns once the work is enqueued; the result is valid when that stream reaches this point.  The
+ * evaluation scratch is shared with the context's other blocking and device calls, which are
+ * ordered after it by an event. */
 hawkes_status hawkes_grad_device(hawkes_ctx* ctx, int32_t id, const hawkes_params* p, int precision,
                                  double* d_out7, void* hip_stream);
 

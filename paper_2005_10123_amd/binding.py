@@ -193,10 +193,10 @@ class Context:
         return {"lambda": out[:, 0].copy(), "Lambda": out[:, 1].copy(), "ell": out[:, 2].copy(),
                 "pi": out[:, 3].copy(), "grad": out[:, 4:10].copy()}
 
-    def grad_device(self, ds, theta, precision, d_out7_ptr: int, stream_ptr=None):
+    def grad_device(self, ds, theta, precision, d_out7_ptr: int, stream_ptr=0):
+        """Enqueue on the hipStream_t `stream_ptr` (0: the null stream)."""
         _check(self.lib.hawkes_grad_device(self._h, _id(ds), ctypes.byref(params(theta)), _prec(precision),
-                                           ctypes.c_void_p(d_out7_ptr),
-                                           ctypes.c_void_p(stream_ptr) if stream_ptr else None))
+                                           ctypes.c_void_p(d_out7_ptr), ctypes.c_void_p(stream_ptr or None)))
 
     def info(self, ds):
         n = ctypes.c_int64()

@@ -88,5 +88,7 @@ void free_dataset(hawkes_ctx* c, Dataset& d);
 
 hawkes_status server_start(hawkes_ctx* c);
 void server_stop(hawkes_ctx* c);
+// Free the serving pool's idle scratch buffers (caller holds c->mu).
+void server_trim(hawkes_ctx* c);
 
 }  // namespace hawkes

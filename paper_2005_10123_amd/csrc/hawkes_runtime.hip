@@ -142,6 +142,17 @@ void dev_free(hawkes_ctx* c, void* p, size_t bytes)
     c->used -= bytes;
 }
 
+// Blocking-call scratch: on budget exhaustion the serving pool's idle buffers are given back first.
+hawkes_status reserve_blocking(hawkes_ctx* c, size_t need)
+{
+    hawkes_status st = c->blk.reserve(c, need);
+    if (st == HAWKES_ENOMEM) {
+        server_trim(c);
+        st = c->blk.reserve(c, need);
+    }
+    return st;
+}
+
 hawkes_status Scratch::reserve(hawkes_ctx* c, size_t need)
 {
     if (need <= bytes) return HAWKES_OK;
@@ -279,7 +290,7 @@ hawkes_status blocking_eval(hawkes_ctx* c, int32_t id, const hawkes_params* p, i
     if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
     const bool want_rows = host_rows != nullptr;
     const Plan pl = make_plan(d->n, d->npad, grad);
-    if ((st = c->blk.reserve(c, scratch_bytes(pl, d->n, want_rows))) != HAWKES_OK) return st;
+    if ((st = reserve_blocking(c, scratch_bytes(pl, d->n, want_rows))) != HAWKES_OK) return st;
     hipStream_t s = c->stream;
     hipError_t e = hipStreamWaitEvent(s, c->blk_free, 0);
     if (e != hipSuccess) return poison(c, hip_fail(e, "hipStreamWaitEvent"));
@@ -548,8 +559,8 @@ hawkes_status hawkes_grad_device(hawkes_ctx* c, int32_t id, const hawkes_params*
     Dataset* d = find_dataset(c, id);
     if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
     const Plan pl = make_plan(d->n, d->npad, true);
-    if ((st = c->blk.reserve(c, scratch_bytes(pl, d->n, false))) != HAWKES_OK) return st;
-    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : c->stream;
+    if ((st = reserve_blocking(c, scratch_bytes(pl, d->n, false))) != HAWKES_OK) return st;
+    hipStream_t s = (hipStream_t)hip_stream;  // NULL: the null stream
     // The scratch is shared with every other blocking or device call of this context.
     hipError_t e = hipStreamWaitEvent(s, c->blk_free, 0);
     if (e != hipSuccess) return poison(c, hip_fail(e, "hipStreamWaitEvent"));

@@ -304,6 +304,14 @@ hawkes_status server_start(hawkes_ctx* c)
     return HAWKES_OK;
 }
 
+void server_trim(hawkes_ctx* c)
+{
+    Server* sv = c->server;
+    if (!sv) return;
+    for (auto& b : sv->pool)
+        if (!b.busy && b.s.base) b.s.release(c);
+}
+
 void server_stop(hawkes_ctx* c)
 {
     Server* sv = c->server;

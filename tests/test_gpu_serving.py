@@ -1,0 +1,118 @@
+"""Batched serving through hawkes_submit / hawkes_poll: each result equals the blocking evaluation
+alone (bitwise: same plan, same arithmetic) whatever it is batched with; invalid requests fail
+alone; a small HBM budget queues work instead of failing; destroying a busy dataset is refused."""
+import numpy as np
+import pytest
+
+from paper_2005_10123_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def datasets(ctx, sizes, seed0=40):
+    out = []
+    for k, n in enumerate(sizes):
+        spec = synth.SimSpec(n, 10.0, 1000.0, 3, 0.5, 0.1, 0.3, (10123, seed0, k))
+        out.append(ctx.dataset(*synth.simulate(spec)))
+    return out
+
+
+def drain(ctx, count, timeout_s=60.0):
+    import time
+
+    got = {}
+    end = time.time() + timeout_s
+    while len(got) < count:
+        assert time.time() < end, "serving did not complete in time"
+        for r in ctx.poll(cap=256, timeout_us=100000):
+            got[r.tag] = r
+    return got
+
+
+def test_alone_equals_mix():
+    ctx = binding.Context(0)
+    dss = datasets(ctx, [3000, 700, 9000, 1500])
+    rng = np.random.default_rng(1)
+    theta0 = np.array(synth.THETA_CFG1)
+    reqs = []
+    for k in range(48):
+        th = theta0 * np.exp(0.1 * rng.standard_normal(6))
+        prec = "fp32c" if k % 3 else "fp64"
+        reqs.append(binding.request(dss[k % 4], th, prec, want_grad=(k % 5 != 0), tag=k))
+    # Submitted in several bursts so later requests join while earlier launches run.
+    ctx.submit(reqs[:5])
+    ctx.submit(reqs[5:20])
+    ctx.submit(reqs[20:])
+    got = drain(ctx, len(reqs))
+    for r in reqs:
+        res = got[r.tag]
+        assert res.status == 0
+        prec = "fp64" if r.precision == binding.FP64 else "fp32c"
+        if r.want_grad:
+            ell, g = ctx.grad(r.dataset, r.p, prec)
+            assert res.loglik == ell and np.array_equal(np.array(res.grad[:]), g), r.tag
+        else:
+            ell = ctx.loglik(r.dataset, r.p, prec)
+            assert res.loglik == ell and all(v == 0.0 for v in res.grad), r.tag
+        assert res.t_done_ns >= res.t_submit_ns
+    assert ctx.outstanding() == 0
+    for d in dss:
+        d.close()
+    ctx.close()
+
+
+def test_bad_requests_fail_alone():
+    ctx = binding.Context(0)
+    (ds,) = datasets(ctx, [1200])
+    good = binding.request(ds, synth.THETA_CFG1, "fp32c", True, tag=1)
+    bad_theta = binding.request(ds, (1.0, -0.5, 20.0, 0.3, 0.5, 0.1), "fp32c", True, tag=2)
+    bad_ds = binding.request(9999, synth.THETA_CFG1, "fp32c", True, tag=3)
+    bad_prec = binding.request(ds, synth.THETA_CFG1, 7, True, tag=4)
+    ctx.submit([good, bad_theta, bad_ds, bad_prec])
+    got = drain(ctx, 4)
+    assert got[1].status == 0
+    assert got[2].status == binding.HAWKES_EINVAL
+    assert got[3].status == binding.HAWKES_ENOTFOUND
+    assert got[4].status == binding.HAWKES_EINVAL
+    ell, g = ctx.grad(ds, synth.THETA_CFG1, "fp32c")
+    assert got[1].loglik == ell
+    ds.close()
+    ctx.close()
+
+
+def test_budget_queues_instead_of_failing():
+    # A budget that holds the datasets and roughly one request's scratch at a time.
+    ctx = binding.Context(0, hbm_budget=48 << 20)
+    dss = datasets(ctx, [20000, 20000], seed0=41)
+    reqs = [binding.request(dss[k % 2], synth.THETA_CFG1, "fp32c", True, tag=k) for k in range(12)]
+    ctx.submit(reqs)
+    got = drain(ctx, len(reqs))
+    ref = [ctx.grad(d, synth.THETA_CFG1, "fp32c")[0] for d in dss]
+    for k in range(12):
+        assert got[k].status == 0
+        assert got[k].loglik == ref[k % 2]
+    for d in dss:
+        d.close()
+    ctx.close()
+
+
+def test_request_that_can_never_fit():
+    ctx = binding.Context(0, hbm_budget=12 << 20)
+    (ds,) = datasets(ctx, [60000], seed0=42)
+    ctx.submit([binding.request(ds, synth.THETA_CFG1, "fp32c", True, tag=5)])
+    got = drain(ctx, 1)
+    assert got[5].status == binding.HAWKES_ENOMEM
+    ds.close()
+    ctx.close()
+
+
+def test_dataset_busy_while_requests_in_flight():
+    ctx = binding.Context(0)
+    (ds,) = datasets(ctx, [40000], seed0=43)
+    ctx.submit([binding.request(ds, synth.THETA_CFG1, "fp64", True, tag=k) for k in range(8)])
+    with pytest.raises(binding.HawkesError) as e:
+        ds.close()
+    assert e.value.status == binding.HAWKES_EBUSY
+    drain(ctx, 8)
+    ds.close()
+    ctx.close()
