@@ -154,6 +154,16 @@ hawkes_status hawkes_poll(hawkes_ctx* ctx, hawkes_result* out, int32_t cap, int3
 /* Requests submitted but not yet returned by hawkes_poll. */
 hawkes_status hawkes_outstanding(hawkes_ctx* ctx, int64_t* n);
 
+/* ---- enumeration of the pair terms ----------------------------------------------------------
+ * HAWKES_PAIRS_SYMMETRIC (default): each unordered pair once.  The background kernel of the
+ *   log-likelihood equation is symmetric in (n, n'), so one evaluation of it feeds both lambda_n
+ *   and lambda_n'; the trigger term feeds only the later event.  Same sums, about half the work.
+ * HAWKES_PAIRS_DIRECT: every ordered pair (n, n'), the enumeration of the paper's Algorithm 3.
+ * Both give the same result up to rounding; a context's choice applies to calls and requests
+ * made after it is set. */
+enum { HAWKES_PAIRS_SYMMETRIC = 0, HAWKES_PAIRS_DIRECT = 1 };
+hawkes_status hawkes_set_pair_scheme(hawkes_ctx* ctx, int scheme);
+
 /* ---- diagnostics -------------------------------------------------------------------------- */
 
 /* Thread-local message describing the calling thread's last failure ("" if none). */

@@ -27,6 +27,9 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EBUSY", -4: "EAGAIN", 
                 -6: "ENOTFOUND", -7: "ECANCELED"}
 FP64 = 0
 FP32C = 1
+PAIRS_SYMMETRIC = 0
+PAIRS_DIRECT = 1
+SCHEMES = {"symmetric": PAIRS_SYMMETRIC, "direct": PAIRS_DIRECT}
 PRECISIONS = {"fp64": FP64, "fp32c": FP32C}
 ROW_FIELDS = 10
 PARAM_NAMES = ("mu0", "tau_x", "tau_t", "theta", "omega", "h")
@@ -98,6 +101,7 @@ def load(path: str | None = None):
         "hawkes_outstanding": ([vp, ctypes.POINTER(i64)], i32),
         "hawkes_last_error": ([], ctypes.c_char_p),
         "hawkes_profile": ([vp, ctypes.c_int], i32),
+        "hawkes_set_pair_scheme": ([vp, ctypes.c_int], i32),
         "hawkes_kernel_time": ([vp, _dp, ctypes.POINTER(i64), ctypes.c_int], i32),
     }
     for name, (args, res) in sig.items():
@@ -223,6 +227,10 @@ class Context:
         n = ctypes.c_int64()
         _check(self.lib.hawkes_outstanding(self._h, ctypes.byref(n)))
         return n.value
+
+    def set_pair_scheme(self, scheme="symmetric"):
+        """"symmetric" (default: each unordered pair once) or "direct" (every ordered pair)."""
+        _check(self.lib.hawkes_set_pair_scheme(self._h, SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)))
 
     # -- diagnostics ---------------------------------------------------------------------------
     def profile(self, enable=True):

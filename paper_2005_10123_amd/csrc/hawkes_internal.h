@@ -27,16 +27,30 @@ constexpr double kSentinel = 1.0e18;
 
 enum Precision : int { kFP64 = 0, kFP32C = 1 };
 
+// How the pair terms are enumerated.
+//   kDirect   : every ordered pair (i, j), as in the paper's Algorithm 3; column ranges of a row
+//               block are split over blocks and each writes per-row partial sums.
+//   kSymmetric: every unordered pair j < i once (lower triangle).  The background kernel B_ij and
+//               its moments are symmetric, so one evaluation feeds both row i and row j; the
+//               trigger term only ever feeds the later event i.  Work units are (row block I,
+//               column tile t <= diagonal) in row-major order, dealt out in equal contiguous
+//               ranges to a grid sized to the device's resident blocks.
+enum Scheme : int { kDirect = 0, kSymmetric = 1 };
+
 // One evaluation's view of its dataset and scratch, passed by value in the kernel arguments.
 struct PairReq {
     const float4* ev32;
     const double4* ev64;
     const int* cut;
-    double* part;         // [splits][K][npad] per-row partial sums, K = 6 (grad) or 2
+    double* part;         // direct: [splits][K][npad]; symmetric: [blocks + row_blocks][K][kRowsPerBlock]
+    double* colpart;      // symmetric: [KC][col_stride] column sums of row block I at RB*I(I+1)/2 + j
+    long long units;      // symmetric: row_blocks (row_blocks + 1) / 2 * (kRowsPerBlock / kTile)
+    long long col_stride; // symmetric: kRowsPerBlock * row_blocks (row_blocks + 1) / 2
     int n, npad;
     int row_blocks;       // npad / kRowsPerBlock
-    int splits;           // column ranges the j loop is cut into
-    int tiles_per_split;  // kTile-event tiles in each column range
+    int splits;           // direct: column ranges the j loop is cut into
+    int tiles_per_split;  // direct: kTile-event tiles in each column range
+    int upb;              // symmetric: work units per block
     int item_begin;       // first work item (block) of this request in the launch
     // Negated base-2 exponent coefficients: B = 2^(nab r^2 + nbb dt^2), E = 2^(nae r^2 + nbe dt).
     // The FP32C pass works in scaled time dt' = ts dt with ts = tsh + tsl = sqrt(-nbb):
@@ -54,10 +68,13 @@ struct PairBatch {
 struct EpiReq {
     const double4* ev64;
     const double* part;
+    const double* colpart;  // symmetric scheme only
+    long long col_stride;
     double* rows_out;     // [n][kRowOut] in sorted order, or nullptr
     double* block_part;   // [nblocks][7]
     double* out7;         // 7 doubles: ell, gradient
     int n, npad, splits, grad;
+    int scheme, row_blocks, upb;
     int nblocks;          // ceil(n / kThreads)
     int item_begin;
     double T;             // largest event time
@@ -73,7 +90,9 @@ struct EpiBatch {
 };
 
 // Kernel launchers (hawkes_kernels.hip).  Each returns the launch's hipError_t.
-hipError_t launch_pair(const PairBatch& b, int precision, bool grad, hipStream_t s);
+hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme, hipStream_t s);
+// Resident blocks per CU of the symmetric pairwise kernel (for sizing its grid).
+int sym_blocks_per_cu(int precision, bool grad);
 hipError_t launch_epilogue(const EpiBatch& b, hipStream_t s);
 hipError_t launch_final(const EpiBatch& b, hipStream_t s);
 

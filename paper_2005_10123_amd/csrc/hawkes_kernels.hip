@@ -335,6 +335,444 @@ __global__ __launch_bounds__(kThreads) void pair_fp64(const PairBatch batch)
 }
 
 // ------------------------------------------------------------------------------------------------
+// Symmetric pairwise pass: every unordered pair j < i (time-sorted indices) once.
+//
+// A block walks a contiguous range of work units (row block I, column tile t) in row-major order
+// over the lower triangle.  For each tile a lane forms its rows' pair terms with each column; the
+// background term B and its moments go both to the lane's row sums (registers) and to the
+// column's sums; the trigger term only to the row (the column is the earlier event).  Column sums
+// are reduced over the 64 lanes 4 columns at a time by a transposing tree (below), combined over
+// the block's 4 waves in LDS in a fixed order, and written once per (row block, column).  Row sums
+// are written once per (block, row block) the block touched.  Tiles below a wave's rows need no
+// mask for B; tiles straddling them mask j >= i; tiles above are skipped.
+
+enum SymMode : int { kSkip = 0, kFullLow = 1, kMaskLow = 2, kDiag = 3 };
+
+// v_permlane32_swap exchanges the upper 32 lanes of the first register with the lower 32 lanes
+// of the second; v_permlane16_swap exchanges the odd 16-lane rows of the first with the even rows
+// of the second.  Written as inline assembly with both registers as outputs (the compiler
+// builtin's second result is not reliable); the s_nops cover the VALU-to-permlane hazards.
+__device__ __forceinline__ void swap32(float& a, float& b)
+{
+    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void swap16(float& a, float& b)
+{
+    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v)
+{
+    const uint2 u = __builtin_bit_cast(uint2, v);
+    uint2 r;
+    r.x = (unsigned)__builtin_amdgcn_update_dpp(0, (int)u.x, CTRL, 0xF, 0xF, false);
+    r.y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)u.y, CTRL, 0xF, 0xF, false);
+    return __builtin_bit_cast(double, r);
+}
+__device__ __forceinline__ void swap32(double& a, double& b)
+{
+    uint2 ua = __builtin_bit_cast(uint2, a), ub = __builtin_bit_cast(uint2, b);
+    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\tv_permlane32_swap_b32 %2, %3\n\ts_nop 1"
+        : "+v"(ua.x), "+v"(ub.x), "+v"(ua.y), "+v"(ub.y));
+    a = __builtin_bit_cast(double, ua);
+    b = __builtin_bit_cast(double, ub);
+}
+__device__ __forceinline__ void swap16(double& a, double& b)
+{
+    uint2 ua = __builtin_bit_cast(uint2, a), ub = __builtin_bit_cast(uint2, b);
+    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\tv_permlane16_swap_b32 %2, %3\n\ts_nop 1"
+        : "+v"(ua.x), "+v"(ub.x), "+v"(ua.y), "+v"(ub.y));
+    a = __builtin_bit_cast(double, ua);
+    b = __builtin_bit_cast(double, ub);
+}
+
+// Sum over the 64 lanes of v0..v3 (four columns); lane l receives the total of column l / 16.
+// The swaps pair lane l with l + 32 (then l + 16) while handing half of the columns to each side,
+// so the two exchange steps cost one add per column pair; rotations by 8, 4, 2, 1 within each
+// 16-lane row finish the sum.  10 operations per four columns.
+template <typename T>
+__device__ __forceinline__ T reduce4(T v0, T v1, T v2, T v3)
+{
+    swap32(v0, v2);
+    swap32(v1, v3);
+    T a0 = v0 + v2, a1 = v1 + v3;
+    swap16(a0, a1);
+    T z = a0 + a1;
+    if constexpr (sizeof(T) == 4) {
+        z += dpp_f<0x128>(z);  // row_ror:8
+        z += dpp_f<0x124>(z);  // row_ror:4
+        z += dpp_f<0x122>(z);  // row_ror:2
+        z += dpp_f<0x121>(z);  // row_ror:1
+    } else {
+        z += dpp_d<0x128>(z);
+        z += dpp_d<0x124>(z);
+        z += dpp_d<0x122>(z);
+        z += dpp_d<0x121>(z);
+    }
+    return z;
+}
+
+// First work unit of each row block: u(I, 0) = TB I (I + 1) / 2, TB tiles per row block.
+__device__ __forceinline__ long long sym_unit0(int I)
+{
+    constexpr long long TB = kRowsPerBlock / kTile;
+    return TB * (long long)I * (I + 1) / 2;
+}
+
+__device__ __forceinline__ int sym_row_block(long long u)
+{
+    constexpr double TB = kRowsPerBlock / kTile;
+    int I = (int)((sqrt(8.0 * (double)u / TB + 1.0) - 1.0) * 0.5);
+    while (sym_unit0(I + 1) <= u) ++I;
+    while (sym_unit0(I) > u) --I;
+    return I;
+}
+
+// One tile of the FP32C symmetric pass for one wave.
+template <int MODE, bool GRAD>
+__device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int j0, int lrow0,
+                                              const float (&xh)[kRowsPerLane], const float (&yh)[kRowsPerLane],
+                                              const float (&xl)[kRowsPerLane], const float (&yl)[kRowsPerLane],
+                                              const float (&ti)[kRowsPerLane], const int (&ct)[kRowsPerLane],
+                                              float t0h, float t0l, float tsh, float tsl, float nab, float nae,
+                                              float kte, float (&s)[6][kRowsPerLane], float (&c)[6][kRowsPerLane],
+                                              float* __restrict__ colw, int lane)
+{
+    constexpr int R = kRowsPerLane;
+    constexpr int K = GRAD ? 6 : 2;
+    constexpr int KC = GRAD ? 3 : 1;
+    for (int ch = 0; ch < kTile; ch += kChunk) {
+        float p[6][R];
+#pragma unroll
+        for (int k = 0; k < 6; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[k][r] = 0.0f;
+#pragma unroll 1
+        for (int g = ch; g < ch + kChunk; g += 4) {
+            float cp[3][4];
+#pragma unroll
+            for (int q = 0; q < 3; ++q)
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) cp[q][cc] = 0.0f;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const float4 hi = sj[2 * (g + cc)];
+                const float4 lo = sj[2 * (g + cc) + 1];
+                const float tu = (hi.z - t0h) + (lo.z - t0l);
+                const float tj = fmaf(tu, tsh, tu * tsl);
+                const int j = j0 + g + cc;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float dx = (xh[r] - hi.x) + (xl[r] - lo.x);
+                    const float dy = (yh[r] - hi.y) + (yl[r] - lo.y);
+                    const float dt = ti[r] - tj;
+                    const float r2 = fmaf(dx, dx, dy * dy);
+                    const float dt2 = dt * dt;
+                    float ab = fmaf(r2, nab, -dt2);
+                    if (MODE == kDiag) ab = (j < lrow0 + r) ? ab : -INFINITY;
+                    const float b = __builtin_amdgcn_exp2f(ab);
+                    p[0][r] += b;
+                    cp[0][cc] += b;
+                    if (GRAD) {
+                        p[1][r] = fmaf(r2, b, p[1][r]);
+                        p[2][r] = fmaf(dt2, b, p[2][r]);
+                        cp[1][cc] = fmaf(r2, b, cp[1][cc]);
+                        cp[2][cc] = fmaf(dt2, b, cp[2][cc]);
+                    }
+                    float ae = fmaf(r2, nae, dt * kte);
+                    if (MODE != kFullLow) ae = (j < ct[r]) ? ae : -INFINITY;
+                    const float e = __builtin_amdgcn_exp2f(ae);
+                    const int ke = GRAD ? 3 : 1;
+                    p[ke][r] += e;
+                    if (GRAD) {
+                        p[4][r] = fmaf(dt, e, p[4][r]);
+                        p[5][r] = fmaf(r2, e, p[5][r]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < KC; ++q) {
+                const float v = reduce4(cp[q][0], cp[q][1], cp[q][2], cp[q][3]);
+                if ((lane & 15) == 0) colw[q * kTile + g + (lane >> 4)] = v;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r) two_sum_into(s[k][r], c[k][r], p[k][r]);
+    }
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(kThreads) void pair_sym_fp32c(const PairBatch batch)
+{
+    constexpr int R = kRowsPerLane;
+    constexpr int K = GRAD ? 6 : 2;
+    constexpr int KC = GRAD ? 3 : 1;
+    constexpr int TB = kRowsPerBlock / kTile;
+    __shared__ float4 sj[2 * kTile];
+    __shared__ float colred[4][KC][kTile];
+
+    const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
+    const PairReq& rq = batch.r[q];
+    const int blk = (int)blockIdx.x - rq.item_begin;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = rq.n;
+    long long u = (long long)blk * rq.upb;
+    const long long uend = min(u + (long long)rq.upb, rq.units);
+    int I = sym_row_block(u);
+    int tile = (int)(u - sym_unit0(I));
+
+    const float tsh = in_vgpr(rq.tsh), tsl = in_vgpr(rq.tsl), nab = in_vgpr(rq.nab);
+    const float nae = in_vgpr(rq.nae), kte = in_vgpr(rq.kte);
+    float xh[R], yh[R], xl[R], yl[R], ti[R];
+    int ct[R];
+    float t0h = 0.0f, t0l = 0.0f;
+    float s[6][R], c[6][R];
+    int cur = -1, w0 = 0, lrow0 = 0, clo = 0;
+    bool active = false;
+
+    for (; u < uend; ++u) {
+        if (I != cur) {
+            if (cur >= 0) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
+                            (double)s[k][r] + (double)c[k][r];
+            }
+            cur = I;
+            w0 = I * kRowsPerBlock + wave * (64 * R);
+            lrow0 = w0 + R * lane;
+            active = w0 < n;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = lrow0 + r;
+                const float4 a = rq.ev32[2 * (size_t)i];
+                const float4 b = rq.ev32[2 * (size_t)i + 1];
+                if (r == 0) {
+                    t0h = a.z;
+                    t0l = b.z;
+                }
+                xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
+                const float tu = (a.z - t0h) + (b.z - t0l);
+                ti[r] = fmaf(tu, tsh, tu * tsl);
+                ct[r] = rq.cut[i];
+            }
+            clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r) s[k][r] = c[k][r] = 0.0f;
+        }
+        const int j0 = tile * kTile;
+        __syncthreads();
+        const float4* src = rq.ev32 + 2 * (size_t)(j0 + threadIdx.x);
+        sj[2 * threadIdx.x] = src[0];
+        sj[2 * threadIdx.x + 1] = src[1];
+        __syncthreads();
+        int mode;
+        if (!active || j0 >= w0 + 64 * R) mode = kSkip;
+        else if (j0 + kTile <= w0) mode = (j0 + kTile <= clo) ? kFullLow : kMaskLow;
+        else mode = kDiag;
+        float* colw = &colred[wave][0][0];
+        if (mode == kSkip) {
+#pragma unroll
+            for (int qq = 0; qq < KC; ++qq)
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
+        } else if (mode == kFullLow) {
+            sym_tile_fp32<kFullLow, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, c, colw, lane);
+        } else if (mode == kMaskLow) {
+            sym_tile_fp32<kMaskLow, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, c, colw, lane);
+        } else {
+            sym_tile_fp32<kDiag, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, c, colw, lane);
+        }
+        __syncthreads();
+        // Column totals of this tile over the block's four waves, in wave order.
+        const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;
+#pragma unroll
+        for (int qq = 0; qq < KC; ++qq)
+            rq.colpart[qq * rq.col_stride + cb] = (double)colred[0][qq][threadIdx.x] + (double)colred[1][qq][threadIdx.x] +
+                                                  (double)colred[2][qq][threadIdx.x] + (double)colred[3][qq][threadIdx.x];
+        if (++tile == TB * (I + 1)) {
+            tile = 0;
+            ++I;
+        }
+    }
+    if (cur >= 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
+                    (double)s[k][r] + (double)c[k][r];
+    }
+}
+
+// FP64 symmetric pass: same walk, binary64 pair terms and plain binary64 sums.
+template <int MODE, bool GRAD>
+__device__ __forceinline__ void sym_tile_fp64(const double4* __restrict__ sj, int j0, int lrow0,
+                                              const double (&x)[kRowsPerLane], const double (&y)[kRowsPerLane],
+                                              const double (&t)[kRowsPerLane], const int (&ct)[kRowsPerLane],
+                                              double nab, double nbb, double nae, double nbe,
+                                              double (&a)[6][kRowsPerLane], double* __restrict__ colw, int lane)
+{
+    constexpr int R = kRowsPerLane;
+    constexpr int KC = GRAD ? 3 : 1;
+#pragma unroll 1
+    for (int g = 0; g < kTile; g += 4) {
+        double cp[3][4];
+#pragma unroll
+        for (int q = 0; q < 3; ++q)
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) cp[q][cc] = 0.0;
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) {
+            const double4 e = sj[g + cc];
+            const int j = j0 + g + cc;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double dx = x[r] - e.x;
+                const double dy = y[r] - e.y;
+                const double dt = t[r] - e.z;
+                const double r2 = fma(dx, dx, dy * dy);
+                const double dt2 = dt * dt;
+                double ab = fma(r2, nab, dt2 * nbb);
+                if (MODE == kDiag) ab = (j < lrow0 + r) ? ab : -INFINITY;
+                const double b = exp2_f64(ab);
+                a[0][r] += b;
+                cp[0][cc] += b;
+                if (GRAD) {
+                    a[1][r] = fma(r2, b, a[1][r]);
+                    a[2][r] = fma(dt2, b, a[2][r]);
+                    cp[1][cc] = fma(r2, b, cp[1][cc]);
+                    cp[2][cc] = fma(dt2, b, cp[2][cc]);
+                }
+                double ae = fma(r2, nae, dt * nbe);
+                if (MODE != kFullLow) ae = (j < ct[r]) ? ae : -INFINITY;
+                const double ex = exp2_f64(ae);
+                const int ke = GRAD ? 3 : 1;
+                a[ke][r] += ex;
+                if (GRAD) {
+                    a[4][r] = fma(dt, ex, a[4][r]);
+                    a[5][r] = fma(r2, ex, a[5][r]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < KC; ++q) {
+            const double v = reduce4(cp[q][0], cp[q][1], cp[q][2], cp[q][3]);
+            if ((lane & 15) == 0) colw[q * kTile + g + (lane >> 4)] = v;
+        }
+    }
+}
+
+template <bool GRAD>
+__global__ __launch_bounds__(kThreads) void pair_sym_fp64(const PairBatch batch)
+{
+    constexpr int R = kRowsPerLane;
+    constexpr int K = GRAD ? 6 : 2;
+    constexpr int KC = GRAD ? 3 : 1;
+    constexpr int TB = kRowsPerBlock / kTile;
+    __shared__ double4 sj[kTile];
+    __shared__ double colred[4][KC][kTile];
+
+    const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
+    const PairReq& rq = batch.r[q];
+    const int blk = (int)blockIdx.x - rq.item_begin;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = rq.n;
+    long long u = (long long)blk * rq.upb;
+    const long long uend = min(u + (long long)rq.upb, rq.units);
+    int I = sym_row_block(u);
+    int tile = (int)(u - sym_unit0(I));
+
+    double x[R], y[R], t[R];
+    int ct[R];
+    double a[6][R];
+    int cur = -1, w0 = 0, lrow0 = 0, clo = 0;
+    bool active = false;
+
+    for (; u < uend; ++u) {
+        if (I != cur) {
+            if (cur >= 0) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) {
+                    const int ka = GRAD ? k : (k == 0 ? 0 : 1);
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] = a[ka][r];
+                }
+            }
+            cur = I;
+            w0 = I * kRowsPerBlock + wave * (64 * R);
+            lrow0 = w0 + R * lane;
+            active = w0 < n;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double4 e = rq.ev64[lrow0 + r];
+                x[r] = e.x; y[r] = e.y; t[r] = e.z;
+                ct[r] = rq.cut[lrow0 + r];
+            }
+            clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
+#pragma unroll
+            for (int k = 0; k < 6; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r) a[k][r] = 0.0;
+        }
+        const int j0 = tile * kTile;
+        __syncthreads();
+        sj[threadIdx.x] = rq.ev64[j0 + threadIdx.x];
+        __syncthreads();
+        int mode;
+        if (!active || j0 >= w0 + 64 * R) mode = kSkip;
+        else if (j0 + kTile <= w0) mode = (j0 + kTile <= clo) ? kFullLow : kMaskLow;
+        else mode = kDiag;
+        double* colw = &colred[wave][0][0];
+        if (mode == kSkip) {
+#pragma unroll
+            for (int qq = 0; qq < KC; ++qq)
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0;
+        } else if (mode == kFullLow) {
+            sym_tile_fp64<kFullLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, lane);
+        } else if (mode == kMaskLow) {
+            sym_tile_fp64<kMaskLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, lane);
+        } else {
+            sym_tile_fp64<kDiag, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, lane);
+        }
+        __syncthreads();
+        const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;
+#pragma unroll
+        for (int qq = 0; qq < KC; ++qq)
+            rq.colpart[qq * rq.col_stride + cb] = colred[0][qq][threadIdx.x] + colred[1][qq][threadIdx.x] +
+                                                  colred[2][qq][threadIdx.x] + colred[3][qq][threadIdx.x];
+        if (++tile == TB * (I + 1)) {
+            tile = 0;
+            ++I;
+        }
+    }
+    if (cur >= 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int ka = GRAD ? k : (k == 0 ? 0 : 1);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] = a[ka][r];
+        }
+    }
+}
+
+// ------------------------------------------------------------------------------------------------
 __device__ __forceinline__ double std_normal_cdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
 __device__ __forceinline__ double std_normal_pdf(double z) { return exp(-0.5 * z * z) * 0.39894228040143267794; }
 
@@ -366,14 +804,42 @@ __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     if (i < rq.n) {
         double S[6] = {0, 0, 0, 0, 0, 0};  // Sb, Sbr, Sbt, Se, Set, Ser
-        for (int s = 0; s < rq.splits; ++s) {
-            const double* ps = rq.part + (size_t)s * K * rq.npad + i;
-            if (rq.grad) {
+        if (rq.scheme == kSymmetric) {
+            // Row sums: one partial per block that walked this row block, in block order.
+            constexpr long long TB = kRowsPerBlock / kTile;
+            const int I = i / kRowsPerBlock, rho = i % kRowsPerBlock;
+            const long long bf = TB * I * (I + 1) / 2 / rq.upb;
+            const long long bl = (TB * (I + 1) * (I + 2) / 2 - 1) / rq.upb;
+            for (long long b = bf; b <= bl; ++b) {
+                const double* ps = rq.part + (size_t)(b + I) * K * kRowsPerBlock + rho;
+                if (rq.grad) {
 #pragma unroll
-                for (int k = 0; k < 6; ++k) S[k] += ps[(size_t)k * rq.npad];
-            } else {
-                S[0] += ps[0];
-                S[3] += ps[rq.npad];
+                    for (int k = 0; k < 6; ++k) S[k] += ps[(size_t)k * kRowsPerBlock];
+                } else {
+                    S[0] += ps[0];
+                    S[3] += ps[kRowsPerBlock];
+                }
+            }
+            // Column sums: the background terms with every later event, by row block.
+            for (int J = I; J < rq.row_blocks; ++J) {
+                const double* pc = rq.colpart + (long long)kRowsPerBlock * J * (J + 1) / 2 + i;
+                S[0] += pc[0];
+                if (rq.grad) {
+                    S[1] += pc[rq.col_stride];
+                    S[2] += pc[2 * rq.col_stride];
+                }
+            }
+            S[0] += 1.0;  // the diagonal term B_ii = 1
+        } else {
+            for (int s = 0; s < rq.splits; ++s) {
+                const double* ps = rq.part + (size_t)s * K * rq.npad + i;
+                if (rq.grad) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) S[k] += ps[(size_t)k * rq.npad];
+                } else {
+                    S[0] += ps[0];
+                    S[3] += ps[rq.npad];
+                }
             }
         }
         // Moments in dt were summed in scaled time dt' = t_scale dt.
@@ -433,11 +899,19 @@ __global__ __launch_bounds__(kThreads) void final_sum(const EpiBatch batch)
 
 }  // namespace
 
-hipError_t launch_pair(const PairBatch& b, int precision, bool grad, hipStream_t s)
+hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme, hipStream_t s)
 {
     if (b.total_items <= 0) return hipSuccess;
     const dim3 grid(b.total_items), block(kThreads);
-    if (precision == kFP32C) {
+    if (scheme == kSymmetric) {
+        if (precision == kFP32C) {
+            if (grad) pair_sym_fp32c<true><<<grid, block, 0, s>>>(b);
+            else pair_sym_fp32c<false><<<grid, block, 0, s>>>(b);
+        } else {
+            if (grad) pair_sym_fp64<true><<<grid, block, 0, s>>>(b);
+            else pair_sym_fp64<false><<<grid, block, 0, s>>>(b);
+        }
+    } else if (precision == kFP32C) {
         if (grad) pair_fp32c<true><<<grid, block, 0, s>>>(b);
         else pair_fp32c<false><<<grid, block, 0, s>>>(b);
     } else {
@@ -445,6 +919,19 @@ hipError_t launch_pair(const PairBatch& b, int precision, bool grad, hipStream_t
         else pair_fp64<false><<<grid, block, 0, s>>>(b);
     }
     return hipGetLastError();
+}
+
+int sym_blocks_per_cu(int precision, bool grad)
+{
+    int nb = 0;
+    hipError_t e;
+    if (precision == kFP32C)
+        e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<true>, kThreads, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<false>, kThreads, 0);
+    else
+        e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<true>, kThreads, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<false>, kThreads, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t launch_epilogue(const EpiBatch& b, hipStream_t s)

@@ -33,8 +33,19 @@ struct Dataset {
 // How one evaluation is cut into blocks; a function of (n, grad) only, so a request's arithmetic
 // is identical whether it runs alone, blocking, or batched with others.
 struct Plan {
+    int scheme = kSymmetric;
     int row_blocks = 0, splits = 0, tiles_per_split = 0, K = 0, epi_blocks = 0;
-    size_t part_doubles = 0;
+    int items = 0;            // blocks of the pairwise kernel
+    int upb = 0;              // symmetric: work units per block
+    long long units = 0;      // symmetric: (row block, column tile) units of the lower triangle
+    long long col_stride = 0; // symmetric: doubles per column-sum quantity
+    size_t part_doubles = 0;  // row partial sums
+    size_t col_doubles = 0;   // symmetric: column partial sums
+};
+
+// One evaluation's scratch carved out of a buffer.
+struct Carved {
+    double *part = nullptr, *colpart = nullptr, *block_part = nullptr, *out7 = nullptr, *rows = nullptr;
 };
 
 struct Scratch {
@@ -67,6 +78,8 @@ struct hawkes_ctx {
     double pair_ms = 0.0;
     int64_t pair_launches = 0;
     hawkes::Server* server = nullptr;
+    int scheme = hawkes::kSymmetric;  // how pair terms are enumerated (hawkes_set_pair_scheme)
+    int sym_slots[2][2] = {{0, 0}, {0, 0}};  // [precision][grad] resident blocks of the symmetric kernel
 };
 
 namespace hawkes {
@@ -75,12 +88,12 @@ extern thread_local std::string g_last_error;
 hawkes_status fail(hawkes_status code, const char* fmt, ...);
 hawkes_status hip_fail(hipError_t e, const char* what);
 hawkes_status check_params(const hawkes_params* p);
-Plan make_plan(int64_t n, int npad, bool grad);
+Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme);
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows);
-void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, PairReq& r);
-void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, EpiReq& e);
-void carve(char* base, const Plan& pl, int64_t n, bool rows, double** part, double** block_part, double** out7,
-           double** rows_out);
+void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const Carved& cv, PairReq& r);
+void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, const Carved& cv,
+              EpiReq& e);
+Carved carve(char* base, const Plan& pl, int64_t n, bool rows);
 hawkes_status dev_alloc(hawkes_ctx* c, void** p, size_t bytes);
 void dev_free(hawkes_ctx* c, void* p, size_t bytes);
 Dataset* find_dataset(hawkes_ctx* c, int32_t id);

@@ -39,10 +39,27 @@ hawkes_status check_params(const hawkes_params* p)
     return HAWKES_OK;
 }
 
-Plan make_plan(int64_t n, int npad, bool grad)
+Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme)
 {
     Plan pl;
+    pl.scheme = scheme;
     pl.row_blocks = npad / kRowsPerBlock;
+    pl.K = grad ? 6 : 2;
+    pl.epi_blocks = (int)((n + kThreads - 1) / kThreads);
+    if (scheme == kSymmetric) {
+        // Equal contiguous ranges of lower-triangle work units, one range per resident block, so
+        // every block of a lone evaluation runs from start to end together with the others.
+        const long long TB = kRowsPerBlock / kTile;
+        const long long T = pl.row_blocks;
+        pl.units = TB * T * (T + 1) / 2;
+        const long long slots = std::max(1, c->sym_slots[precision == kFP32C ? 1 : 0][grad ? 1 : 0]);
+        pl.upb = (int)std::max<long long>(1, (pl.units + slots - 1) / slots);
+        pl.items = (int)((pl.units + pl.upb - 1) / pl.upb);
+        pl.part_doubles = (size_t)(pl.items + T) * pl.K * kRowsPerBlock;
+        pl.col_stride = (long long)kRowsPerBlock * T * (T + 1) / 2;
+        pl.col_doubles = (size_t)(grad ? 3 : 1) * pl.col_stride;
+        return pl;
+    }
     const int tiles = npad / kTile;
     // About eight blocks per compute unit: enough that the spread of per-block work (later rows
     // have more causal columns) leaves a short tail.
@@ -51,15 +68,15 @@ Plan make_plan(int64_t n, int npad, bool grad)
     splits = std::max(1, std::min(splits, std::min(kMaxSplits, tiles)));
     pl.tiles_per_split = (tiles + splits - 1) / splits;
     pl.splits = (tiles + pl.tiles_per_split - 1) / pl.tiles_per_split;
-    pl.K = grad ? 6 : 2;
+    pl.items = pl.row_blocks * pl.splits;
     pl.part_doubles = (size_t)pl.splits * pl.K * npad;
-    pl.epi_blocks = (int)((n + kThreads - 1) / kThreads);
     return pl;
 }
 
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows)
 {
-    size_t b = pl.part_doubles * sizeof(double) + (size_t)pl.epi_blocks * 7 * sizeof(double) + 8 * sizeof(double);
+    size_t b = (pl.part_doubles + pl.col_doubles) * sizeof(double) + (size_t)pl.epi_blocks * 7 * sizeof(double) +
+               8 * sizeof(double);
     if (rows) b += (size_t)n * kRowOut * sizeof(double);
     return b;
 }
@@ -80,14 +97,24 @@ void fold(const hawkes_params& p, PairReq& r)
     r.kte = (float)(r.nbe64 / ((double)r.tsh + (double)r.tsl));
 }
 
-void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, EpiReq& e)
+void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, const Carved& cv,
+              EpiReq& e)
 {
     const double two_pi = 6.28318530717958647693;
     e.ev64 = d.ev64;
+    e.part = cv.part;
+    e.colpart = cv.colpart;
+    e.col_stride = pl.col_stride;
+    e.block_part = cv.block_part;
+    e.out7 = cv.out7;
+    e.rows_out = cv.rows;
     e.n = (int)d.n;
     e.npad = d.npad;
     e.splits = pl.splits;
     e.grad = grad ? 1 : 0;
+    e.scheme = pl.scheme;
+    e.row_blocks = pl.row_blocks;
+    e.upb = pl.upb;
     e.nblocks = pl.epi_blocks;
     e.T = d.T;
     e.mu0 = p.mu0;
@@ -103,16 +130,21 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
     e.t_scale = precision == kFP32C ? (double)folded.tsh + (double)folded.tsl : 1.0;
 }
 
-void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, PairReq& r)
+void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const Carved& cv, PairReq& r)
 {
     r.ev32 = d.ev32;
     r.ev64 = d.ev64;
     r.cut = d.cut;
+    r.part = cv.part;
+    r.colpart = cv.colpart;
+    r.units = pl.units;
+    r.col_stride = pl.col_stride;
     r.n = (int)d.n;
     r.npad = d.npad;
     r.row_blocks = pl.row_blocks;
     r.splits = pl.splits;
     r.tiles_per_split = pl.tiles_per_split;
+    r.upb = pl.upb;
     fold(p, r);
 }
 
@@ -179,44 +211,42 @@ void Scratch::release(hawkes_ctx* c)
     bytes = 0;
 }
 
-// Carve one evaluation's scratch: partial sums, block partials, 7 result doubles, per-row output.
-void carve(char* base, const Plan& pl, int64_t n, bool rows, double** part, double** block_part,
-           double** out7, double** rows_out)
+// Carve one evaluation's scratch: row partials, column partials, block partials, 7 result doubles,
+// per-row output.
+Carved carve(char* base, const Plan& pl, int64_t n, bool rows)
 {
+    Carved cv;
     double* p = (double*)base;
-    *part = p;
+    cv.part = p;
     p += pl.part_doubles;
-    *block_part = p;
+    cv.colpart = pl.col_doubles ? p : nullptr;
+    p += pl.col_doubles;
+    cv.block_part = p;
     p += (size_t)pl.epi_blocks * 7;
-    *out7 = p;
+    cv.out7 = p;
     p += 8;
-    *rows_out = rows ? p : nullptr;
+    cv.rows = rows ? p : nullptr;
+    return cv;
 }
 
 hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params& p, int precision, bool grad,
                            char* scratch, double* out7_override, double** out7_used, double** rows_out,
                            bool want_rows, hipStream_t s)
 {
-    const Plan pl = make_plan(d.n, d.npad, grad);
-    double *part, *bp, *out7, *rows;
-    carve(scratch, pl, d.n, want_rows, &part, &bp, &out7, &rows);
-    if (out7_override) out7 = out7_override;
+    const Plan pl = make_plan(c, d.n, d.npad, grad, precision, c->scheme);
+    Carved cv = carve(scratch, pl, d.n, want_rows);
+    if (out7_override) cv.out7 = out7_override;
 
     PairBatch pb;
     memset(&pb, 0, sizeof pb);
-    fill_pair(p, d, pl, pb.r[0]);
-    pb.r[0].part = part;
+    fill_pair(p, d, pl, cv, pb.r[0]);
     pb.r[0].item_begin = 0;
     pb.nreq = 1;
-    pb.total_items = pl.row_blocks * pl.splits;
+    pb.total_items = pl.items;
 
     EpiBatch eb;
     memset(&eb, 0, sizeof eb);
-    fill_epi(p, d, pl, grad, precision, eb.r[0]);
-    eb.r[0].part = part;
-    eb.r[0].block_part = bp;
-    eb.r[0].out7 = out7;
-    eb.r[0].rows_out = rows;
+    fill_epi(p, d, pl, grad, precision, cv, eb.r[0]);
     eb.r[0].item_begin = 0;
     eb.nreq = 1;
     eb.total_items = pl.epi_blocks;
@@ -226,7 +256,7 @@ hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params&
         e = hipEventRecord(c->prof_ev[0], s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
     }
-    e = launch_pair(pb, precision, grad, s);
+    e = launch_pair(pb, precision, grad, pl.scheme, s);
     if (e != hipSuccess) return hip_fail(e, "pair kernel launch");
     if (c->profile) {
         e = hipEventRecord(c->prof_ev[1], s);
@@ -237,8 +267,8 @@ hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params&
     if (e != hipSuccess) return hip_fail(e, "epilogue launch");
     e = launch_final(eb, s);
     if (e != hipSuccess) return hip_fail(e, "final reduction launch");
-    if (out7_used) *out7_used = out7;
-    if (rows_out) *rows_out = rows;
+    if (out7_used) *out7_used = cv.out7;
+    if (rows_out) *rows_out = cv.rows;
     return HAWKES_OK;
 }
 
@@ -289,7 +319,7 @@ hawkes_status blocking_eval(hawkes_ctx* c, int32_t id, const hawkes_params* p, i
     Dataset* d = find_dataset(c, id);
     if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
     const bool want_rows = host_rows != nullptr;
-    const Plan pl = make_plan(d->n, d->npad, grad);
+    const Plan pl = make_plan(c, d->n, d->npad, grad, precision, c->scheme);
     if ((st = reserve_blocking(c, scratch_bytes(pl, d->n, want_rows))) != HAWKES_OK) return st;
     hipStream_t s = c->stream;
     hipError_t e = hipStreamWaitEvent(s, c->blk_free, 0);
@@ -448,6 +478,11 @@ hawkes_status hawkes_create(int device, size_t hbm_budget_bytes, void* hip_strea
     if ((e = hipEventCreate(&c->prof_ev[1])) != hipSuccess) return hip_fail(e, "hipEventCreate");
     if ((e = hipHostMalloc((void**)&c->h_out7, 8 * sizeof(double), hipHostMallocDefault)) != hipSuccess)
         return hip_fail(e, "hipHostMalloc");
+    int cus = 0;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device)) != hipSuccess)
+        return hip_fail(e, "hipDeviceGetAttribute");
+    for (int prec = 0; prec < 2; ++prec)
+        for (int g = 0; g < 2; ++g) c->sym_slots[prec][g] = cus * sym_blocks_per_cu(prec, g != 0);
     hawkes_status st = server_start(c.get());
     if (st != HAWKES_OK) return st;
     *out = c.release();
@@ -558,7 +593,7 @@ hawkes_status hawkes_grad_device(hawkes_ctx* c, int32_t id, const hawkes_params*
     std::lock_guard<std::mutex> lk(c->mu);
     Dataset* d = find_dataset(c, id);
     if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
-    const Plan pl = make_plan(d->n, d->npad, true);
+    const Plan pl = make_plan(c, d->n, d->npad, true, precision, c->scheme);
     if ((st = reserve_blocking(c, scratch_bytes(pl, d->n, false))) != HAWKES_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;  // NULL: the null stream
     // The scratch is shared with every other blocking or device call of this context.
@@ -569,6 +604,16 @@ hawkes_status hawkes_grad_device(hawkes_ctx* c, int32_t id, const hawkes_params*
     e = hipEventRecord(c->blk_free, s);
     if (e != hipSuccess) return poison(c, hip_fail(e, "hipEventRecord"));
     c->prof_pending = false;  // not waited for here; device calls are not profiled
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_set_pair_scheme(hawkes_ctx* c, int scheme)
+{
+    if (!c) return fail(HAWKES_EINVAL, "ctx is NULL");
+    if (scheme != HAWKES_PAIRS_SYMMETRIC && scheme != HAWKES_PAIRS_DIRECT)
+        return fail(HAWKES_EINVAL, "unknown pair scheme %d", scheme);
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->scheme = scheme == HAWKES_PAIRS_DIRECT ? kDirect : kSymmetric;
     return HAWKES_OK;
 }
 

@@ -195,8 +195,10 @@ void admit(hawkes_ctx* c, Server* sv)
         int nb = 0, items = 0, epi_items = 0;
         std::vector<Pending> back;  // could not get memory now: return to the queue front
         std::vector<hawkes_result> failed;
+        int scheme = kSymmetric;
         {
             std::lock_guard<std::mutex> lk(c->mu);
+            scheme = c->scheme;
             for (size_t k = 0; k < cand.size(); ++k) {
                 const Pending& p = cand[k];
                 Dataset* d = find_dataset(c, p.req.dataset);
@@ -205,7 +207,7 @@ void admit(hawkes_ctx* c, Server* sv)
                     continue;
                 }
                 const bool grad = p.req.want_grad != 0;
-                const Plan pl = make_plan(d->n, d->npad, grad);
+                const Plan pl = make_plan(c, d->n, d->npad, grad, p.req.precision, scheme);
                 const size_t need = scratch_bytes(pl, d->n, false);
                 int bi = back.empty() ? get_buffer(c, sv, need) : -1;
                 if (bi < 0) {
@@ -218,17 +220,12 @@ void admit(hawkes_ctx* c, Server* sv)
                     continue;
                 }
                 sv->pool[bi].busy = true;
-                double *part, *bp, *o7, *rows;
-                carve(sv->pool[bi].s.base, pl, d->n, false, &part, &bp, &o7, &rows);
-                fill_pair(p.req.p, *d, pl, pb.r[nb]);
-                pb.r[nb].part = part;
+                Carved cv = carve(sv->pool[bi].s.base, pl, d->n, false);
+                cv.out7 = L.d_out + 8 * nb;
+                fill_pair(p.req.p, *d, pl, cv, pb.r[nb]);
                 pb.r[nb].item_begin = items;
-                items += pl.row_blocks * pl.splits;
-                fill_epi(p.req.p, *d, pl, grad, p.req.precision, eb.r[nb]);
-                eb.r[nb].part = part;
-                eb.r[nb].block_part = bp;
-                eb.r[nb].out7 = L.d_out + 8 * nb;
-                eb.r[nb].rows_out = nullptr;
+                items += pl.items;
+                fill_epi(p.req.p, *d, pl, grad, p.req.precision, cv, eb.r[nb]);
                 eb.r[nb].item_begin = epi_items;
                 epi_items += pl.epi_blocks;
                 L.req[nb] = p;
@@ -249,7 +246,7 @@ void admit(hawkes_ctx* c, Server* sv)
         sv->next_stream = (sv->next_stream + 1) % kStreams;
         const int prec = L.req[0].req.precision;
         const bool grad = L.req[0].req.want_grad != 0;
-        hipError_t e = launch_pair(pb, prec, grad, s);
+        hipError_t e = launch_pair(pb, prec, grad, scheme, s);
         if (e == hipSuccess) e = launch_epilogue(eb, s);
         if (e == hipSuccess) e = launch_final(eb, s);
         if (e == hipSuccess) e = hipMemcpyAsync(L.h_out, L.d_out, (size_t)nb * 8 * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -11,6 +11,7 @@ import oracle_pins as P
 
 pytestmark = pytest.mark.gpu
 PRECS = ["fp64", "fp32c"]
+SCHEMES = ["symmetric", "direct"]
 
 
 @pytest.fixture(scope="module")
@@ -21,15 +22,19 @@ def ctx():
 
 
 def check_full(ctx, x, y, t, th, what, precs=PRECS):
+    """Both precisions and both pair enumerations against the oracle."""
     ref = oracle.evaluate(x, y, t, th, rows=True)
     ds = ctx.dataset(x, y, t)
     try:
-        for prec in precs:
-            ell, g = ctx.grad(ds, th, prec)
-            assert_close(ell, g, ref, prec, what, th)
-            ell2 = ctx.loglik(ds, th, prec)
-            assert rel(ell2, ref["ell"]) <= TOL[prec], (what, prec, "loglik-only", ell2, ref["ell"])
+        for scheme in SCHEMES:
+            ctx.set_pair_scheme(scheme)
+            for prec in precs:
+                ell, g = ctx.grad(ds, th, prec)
+                assert_close(ell, g, ref, prec, (what, scheme), th)
+                ell2 = ctx.loglik(ds, th, prec)
+                assert rel(ell2, ref["ell"]) <= TOL[prec], (what, scheme, prec, "loglik-only", ell2, ref["ell"])
     finally:
+        ctx.set_pair_scheme("symmetric")
         ds.close()
     return ref
 
