@@ -351,14 +351,15 @@ enum SymMode : int { kSkip = 0, kFullLow = 1, kMaskLow = 2, kDiag = 3 };
 // v_permlane32_swap exchanges the upper 32 lanes of the first register with the lower 32 lanes
 // of the second; v_permlane16_swap exchanges the odd 16-lane rows of the first with the even rows
 // of the second.  Written as inline assembly with both registers as outputs (the compiler
-// builtin's second result is not reliable); the s_nops cover the VALU-to-permlane hazards.
+// builtin's second result is not reliable); the s_nop covers the hazard of a VALU write
+// immediately followed by a permlane read of the same register.
 __device__ __forceinline__ void swap32(float& a, float& b)
 {
-    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
 }
 __device__ __forceinline__ void swap16(float& a, float& b)
 {
-    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)
@@ -377,7 +378,7 @@ __device__ __forceinline__ double dpp_d(double v)
 __device__ __forceinline__ void swap32(double& a, double& b)
 {
     uint2 ua = __builtin_bit_cast(uint2, a), ub = __builtin_bit_cast(uint2, b);
-    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\tv_permlane32_swap_b32 %2, %3\n\ts_nop 1"
+    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\tv_permlane32_swap_b32 %2, %3"
         : "+v"(ua.x), "+v"(ub.x), "+v"(ua.y), "+v"(ub.y));
     a = __builtin_bit_cast(double, ua);
     b = __builtin_bit_cast(double, ub);
@@ -385,7 +386,7 @@ __device__ __forceinline__ void swap32(double& a, double& b)
 __device__ __forceinline__ void swap16(double& a, double& b)
 {
     uint2 ua = __builtin_bit_cast(uint2, a), ub = __builtin_bit_cast(uint2, b);
-    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\tv_permlane16_swap_b32 %2, %3\n\ts_nop 1"
+    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\tv_permlane16_swap_b32 %2, %3"
         : "+v"(ua.x), "+v"(ub.x), "+v"(ua.y), "+v"(ub.y));
     a = __builtin_bit_cast(double, ua);
     b = __builtin_bit_cast(double, ub);
@@ -417,6 +418,47 @@ __device__ __forceinline__ T reduce4(T v0, T v1, T v2, T v3)
     return z;
 }
 
+// reduce4 for KC quantities at once, step by step interleaved so that each dependent DPP step
+// of one quantity is separated by the others' (hides the DPP read-after-write wait states).
+template <int KC, typename T>
+__device__ __forceinline__ void reduce4_multi(T (&cp)[3][4], T (&out)[3])
+{
+    T a0[KC], a1[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+        swap32(cp[q][0], cp[q][2]);
+        swap32(cp[q][1], cp[q][3]);
+    }
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+        a0[q] = cp[q][0] + cp[q][2];
+        a1[q] = cp[q][1] + cp[q][3];
+    }
+#pragma unroll
+    for (int q = 0; q < KC; ++q) swap16(a0[q], a1[q]);
+#pragma unroll
+    for (int q = 0; q < KC; ++q) out[q] = a0[q] + a1[q];
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int q = 0; q < KC; ++q) out[q] += dpp_f<0x128>(out[q]);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) out[q] += dpp_f<0x124>(out[q]);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) out[q] += dpp_f<0x122>(out[q]);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) out[q] += dpp_f<0x121>(out[q]);
+    } else {
+#pragma unroll
+        for (int q = 0; q < KC; ++q) out[q] += dpp_d<0x128>(out[q]);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) out[q] += dpp_d<0x124>(out[q]);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) out[q] += dpp_d<0x122>(out[q]);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) out[q] += dpp_d<0x121>(out[q]);
+    }
+}
+
 // First work unit of each row block: u(I, 0) = TB I (I + 1) / 2, TB tiles per row block.
 __device__ __forceinline__ long long sym_unit0(int I)
 {
@@ -440,7 +482,7 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
                                               const float (&xl)[kRowsPerLane], const float (&yl)[kRowsPerLane],
                                               const float (&ti)[kRowsPerLane], const int (&ct)[kRowsPerLane],
                                               float t0h, float t0l, float tsh, float tsl, float nab, float nae,
-                                              float kte, float (&s)[6][kRowsPerLane], float (&c)[6][kRowsPerLane],
+                                              float kte, float (&s)[6][kRowsPerLane], float* __restrict__ comp,
                                               float* __restrict__ colw, int lane)
 {
     constexpr int R = kRowsPerLane;
@@ -495,21 +537,27 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
                     }
                 }
             }
+            float v[3];
+            reduce4_multi<KC>(cp, v);
+            if ((lane & 15) == 0)
 #pragma unroll
-            for (int q = 0; q < KC; ++q) {
-                const float v = reduce4(cp[q][0], cp[q][1], cp[q][2], cp[q][3]);
-                if ((lane & 15) == 0) colw[q * kTile + g + (lane >> 4)] = v;
-            }
+                for (int q = 0; q < KC; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
         }
 #pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
-            for (int r = 0; r < R; ++r) two_sum_into(s[k][r], c[k][r], p[k][r]);
+            for (int r = 0; r < R; ++r) {
+                float& cc = comp[(k * R + r) * kThreads];
+                two_sum_into(s[k][r], cc, p[k][r]);
+            }
     }
 }
 
+// The compensation terms of the row sums are touched once per 64 columns, so they live in LDS
+// (one float per thread per accumulator, thread-contiguous) rather than in registers; that keeps
+// the kernel within the register budget of three waves per SIMD.
 template <bool GRAD>
-__global__ __launch_bounds__(kThreads) void pair_sym_fp32c(const PairBatch batch)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void pair_sym_fp32c(const PairBatch batch)
 {
     constexpr int R = kRowsPerLane;
     constexpr int K = GRAD ? 6 : 2;
@@ -517,6 +565,8 @@ __global__ __launch_bounds__(kThreads) void pair_sym_fp32c(const PairBatch batch
     constexpr int TB = kRowsPerBlock / kTile;
     __shared__ float4 sj[2 * kTile];
     __shared__ float colred[4][KC][kTile];
+    __shared__ float comp_lds[K * R * kThreads];
+    float* comp = comp_lds + threadIdx.x;
 
     const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
     const PairReq& rq = batch.r[q];
@@ -534,7 +584,7 @@ __global__ __launch_bounds__(kThreads) void pair_sym_fp32c(const PairBatch batch
     float xh[R], yh[R], xl[R], yl[R], ti[R];
     int ct[R];
     float t0h = 0.0f, t0l = 0.0f;
-    float s[6][R], c[6][R];
+    float s[6][R];
     int cur = -1, w0 = 0, lrow0 = 0, clo = 0;
     bool active = false;
 
@@ -546,7 +596,7 @@ __global__ __launch_bounds__(kThreads) void pair_sym_fp32c(const PairBatch batch
 #pragma unroll
                     for (int r = 0; r < R; ++r)
                         rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
-                            (double)s[k][r] + (double)c[k][r];
+                            (double)s[k][r] + (double)comp[(k * R + r) * kThreads];
             }
             cur = I;
             w0 = I * kRowsPerBlock + wave * (64 * R);
@@ -570,7 +620,9 @@ __global__ __launch_bounds__(kThreads) void pair_sym_fp32c(const PairBatch batch
 #pragma unroll
             for (int k = 0; k < 6; ++k)
 #pragma unroll
-                for (int r = 0; r < R; ++r) s[k][r] = c[k][r] = 0.0f;
+                for (int r = 0; r < R; ++r) s[k][r] = 0.0f;
+#pragma unroll
+            for (int k = 0; k < K * R; ++k) comp[k * kThreads] = 0.0f;
         }
         const int j0 = tile * kTile;
         __syncthreads();
@@ -589,11 +641,11 @@ __global__ __launch_bounds__(kThreads) void pair_sym_fp32c(const PairBatch batch
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
         } else if (mode == kFullLow) {
-            sym_tile_fp32<kFullLow, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, c, colw, lane);
+            sym_tile_fp32<kFullLow, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, lane);
         } else if (mode == kMaskLow) {
-            sym_tile_fp32<kMaskLow, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, c, colw, lane);
+            sym_tile_fp32<kMaskLow, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, lane);
         } else {
-            sym_tile_fp32<kDiag, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, c, colw, lane);
+            sym_tile_fp32<kDiag, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, lane);
         }
         __syncthreads();
         // Column totals of this tile over the block's four waves, in wave order.
@@ -613,7 +665,7 @@ __global__ __launch_bounds__(kThreads) void pair_sym_fp32c(const PairBatch batch
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
-                    (double)s[k][r] + (double)c[k][r];
+                    (double)s[k][r] + (double)comp[(k * R + r) * kThreads];
     }
 }
 
@@ -667,11 +719,11 @@ __device__ __forceinline__ void sym_tile_fp64(const double4* __restrict__ sj, in
                 }
             }
         }
+        double v[3];
+        reduce4_multi<KC>(cp, v);
+        if ((lane & 15) == 0)
 #pragma unroll
-        for (int q = 0; q < KC; ++q) {
-            const double v = reduce4(cp[q][0], cp[q][1], cp[q][2], cp[q][3]);
-            if ((lane & 15) == 0) colw[q * kTile + g + (lane >> 4)] = v;
-        }
+            for (int q = 0; q < KC; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
     }
 }
 
