@@ -26,11 +26,31 @@ sys.path.insert(0, ROOT)
 # are causal): 13.5 FP32 lane operations (FMA = 1) and 1.5 exponentials for log-likelihood +
 # gradient; 10.5 and 1.5 for the log-likelihood alone.
 WORK = {True: (13.5, 1.5), False: (10.5, 1.5)}
+# The symmetric enumeration evaluates each unordered pair once: 3 differences, 2 for r^2, 1 for
+# dt^2, 1 background and 2 trigger exponent arguments, the background term and its two moments
+# added to both events (6) and the trigger term and its two moments to the later one (3), i.e.
+# 18 lane operations and 2 exponentials per unordered pair = 9 and 1 per ordered pair.
+WORK_SYM = (9.0, 1.0)
 CUS, CLOCK = 256, 2.4e9
 P_OPS32 = 157.3e12 / 2          # FP32 vector: 157.3 TFLOP/s with FMA = 2 FLOP
 P_OPS64 = 78.6e12 / 2           # FP64 vector
 P_EXP32 = CUS * 32 * CLOCK      # v_exp_f32 lanes per second (32 per CU per clock, measured)
 FP64_EXP_OPS = 16               # FP64 lane operations of one exp2 (range reduction + degree-12 poly)
+
+
+def measured_traffic(kernel_source: str, record: str):
+    """HBM bytes per launch of the pairwise kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    recorded in profiles/ (copy-calibrated), or None when the kernel source changed since."""
+    import hashlib
+
+    try:
+        rec = json.load(open(record))
+        sha = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("kernel_source_sha256") != sha:
+        return None
+    return rec["fetch_bytes"] + rec["write_bytes"]
 
 
 def roofline_pairs(grad: bool, fp64: bool = False) -> float:
@@ -204,10 +224,15 @@ def main():
                                f"theta, omega, h)={tuple(theta)}; fused log-likelihood + gradient, FP32-compensated",
                    "n_events": n, "pairs_per_step": pairs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": roof / 1e9, "unit": "Gpair/s",
-                     "frac": achieved / roof, "traffic": None,
-                     "kernel": "pair_fp32c<grad>", "kernel_ms": kms,
-                     "model": "1/(13.5 ops / 78.65e12 ops/s + 1.5 exp / 19.66e12 exp/s) per pair: FP32 vector "
-                              "157.3 TFLOP/s (FMA=2) and v_exp_f32 at 32 lanes/CU/clk x 256 CU x 2.4 GHz",
+                     "frac": achieved / roof,
+                     "traffic": measured_traffic(os.path.join(ROOT, "paper_2005_10123_amd", "csrc", "hawkes_kernels.hip"),
+                                                 os.path.join(ROOT, "profiles", "pair_sym_fp32c_grad_city85k.json")),
+                     "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
+                     "kernel": "pair_sym_fp32c<grad>", "kernel_ms": kms,
+                     "model": "1/(13.5 ops / 78.65e12 ops/s + 1.5 exp / 19.66e12 exp/s) per ordered pair (the "
+                              "method's work as in the direct enumeration): FP32 vector 157.3 TFLOP/s (FMA=2) and "
+                              "v_exp_f32 at 32 lanes/CU/clk x 256 CU x 2.4 GHz",
+                     "symmetric_model_frac": achieved / (1.0 / (WORK_SYM[0] / P_OPS32 + WORK_SYM[1] / P_EXP32)),
                      "valu_tflops": achieved * 19.0 / 1e12},
         "p50_ms_step": float(np.percentile(per, 50) * 1e3),
         "p99_ms_step": float(np.percentile(per, 99) * 1e3),

@@ -728,7 +728,7 @@ __device__ __forceinline__ void sym_tile_fp64(const double4* __restrict__ sj, in
 }
 
 template <bool GRAD>
-__global__ __launch_bounds__(kThreads) void pair_sym_fp64(const PairBatch batch)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void pair_sym_fp64(const PairBatch batch)
 {
     constexpr int R = kRowsPerLane;
     constexpr int K = GRAD ? 6 : 2;
