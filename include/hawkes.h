@@ -115,6 +115,15 @@ hawkes_status hawkes_grad_device(hawkes_ctx* ctx, int32_t id, const hawkes_param
 hawkes_status hawkes_rows(hawkes_ctx* ctx, int32_t id, const hawkes_params* p, int precision,
                           double* out_rows);
 
+/* Log-likelihood and self-excitation probabilities for `count` parameter vectors over one dataset
+ * (the paper evaluates pi_n for every event under each of 1,000 posterior samples of Theta,
+ * Section 3.2).  thetas: count parameter vectors.  out_loglik: count doubles, or NULL.
+ * out_pi: count * n doubles, or NULL; pi of event k under thetas[s] at out_pi[s * n + k], events in
+ * the caller's original order.  At least one output must be requested.  FP32C shares each pair's
+ * differences among four parameter vectors per pass; FP64 evaluates them one at a time. */
+hawkes_status hawkes_loglik_multi(hawkes_ctx* ctx, int32_t id, const hawkes_params* thetas, int32_t count,
+                                  int precision, double* out_loglik, double* out_pi);
+
 /* ---- batched serving -------------------------------------------------------------------------
  * Requests from many concurrent samplers (the paper's Algorithm 1 evaluates the likelihood once
  * per Metropolis-Hastings step) are queued, admitted while evaluation slots and the HBM budget

@@ -102,6 +102,7 @@ def load(path: str | None = None):
         "hawkes_last_error": ([], ctypes.c_char_p),
         "hawkes_profile": ([vp, ctypes.c_int], i32),
         "hawkes_set_pair_scheme": ([vp, ctypes.c_int], i32),
+        "hawkes_loglik_multi": ([vp, i32, ctypes.POINTER(Params), i32, ctypes.c_int, _dp, _dp], i32),
         "hawkes_kernel_time": ([vp, _dp, ctypes.POINTER(i64), ctypes.c_int], i32),
     }
     for name, (args, res) in sig.items():
@@ -196,6 +197,19 @@ class Context:
                                     out.ctypes.data_as(_dp)))
         return {"lambda": out[:, 0].copy(), "Lambda": out[:, 1].copy(), "ell": out[:, 2].copy(),
                 "pi": out[:, 3].copy(), "grad": out[:, 4:10].copy()}
+
+    def loglik_multi(self, ds, thetas, precision="fp32c", want_pi=True):
+        """Log-likelihoods (S,) and, with want_pi, self-excitation probabilities (S, n) for S
+        parameter vectors (rows of `thetas`)."""
+        th = np.ascontiguousarray(thetas, dtype=np.float64).reshape(-1, 6)
+        S = th.shape[0]
+        n = ds.n if isinstance(ds, Dataset) else int(self.info(ds)[0])
+        arr = (Params * S)(*[params(row) for row in th])
+        ll = np.zeros(S)
+        pi = np.zeros((S, n)) if want_pi else None
+        _check(self.lib.hawkes_loglik_multi(self._h, _id(ds), arr, S, _prec(precision), ll.ctypes.data_as(_dp),
+                                            pi.ctypes.data_as(_dp) if want_pi else None))
+        return (ll, pi) if want_pi else ll
 
     def grad_device(self, ds, theta, precision, d_out7_ptr: int, stream_ptr=0):
         """Enqueue on the hipStream_t `stream_ptr` (0: the null stream)."""

@@ -1,0 +1,441 @@
+// hawkes_multi.hip -- the log-likelihood and the self-excitation probabilities for many parameter
+// vectors over one dataset (arXiv 2005.10123, Section 2.1: the log-likelihood equation and the
+// probability equation pi_n = xi_n / lambda_n; Section 3.2 evaluates pi for 1,000 posterior samples
+// of Theta).
+//
+// FP32C: the symmetric lower-triangle walk of the single-Theta pass, but each pair's differences,
+// r^2 and dt^2 are formed once and shared by kMultiTheta parameter vectors, each with its own two
+// exponentials and running sums (log-likelihood terms only: S_b, S_e).  Time differences are taken
+// from each lane's own first row without a Theta-dependent scale.  FP64: one FP64 evaluation per
+// parameter vector.
+#include "hawkes_device.h"
+#include "hawkes_runtime.h"
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+namespace hawkes {
+
+constexpr int kMultiTheta = 4;
+
+struct MultiReq {
+    const float4* ev32;
+    const int* cut;
+    double* part;     // [blocks + row_blocks][2 * kMultiTheta][kRowsPerBlock]
+    double* colpart;  // [kMultiTheta][col_stride]
+    long long units, col_stride;
+    int n, npad, row_blocks, upb;
+    float nab[kMultiTheta], nbb[kMultiTheta], nae[kMultiTheta], nbe[kMultiTheta];
+};
+
+struct MultiEpi {
+    const double4* ev64;
+    const double* part;
+    const double* colpart;
+    double* pi_out;      // [nth][n] in sorted order, or nullptr
+    double* block_part;  // [nblocks][kMultiTheta]
+    double* out;         // kMultiTheta log-likelihoods
+    long long col_stride;
+    int n, npad, row_blocks, upb, nth, nblocks;
+    double T;
+    double mu0[kMultiTheta], tau_t[kMultiTheta], theta[kMultiTheta], omega[kMultiTheta];
+    double cb[kMultiTheta], ce[kMultiTheta];
+};
+
+namespace {
+
+using namespace dev;
+
+template <int MODE>
+__device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0, int lrow0,
+                                           const float (&xh)[kRowsPerLane], const float (&yh)[kRowsPerLane],
+                                           const float (&xl)[kRowsPerLane], const float (&yl)[kRowsPerLane],
+                                           const float (&ti)[kRowsPerLane], const int (&ct)[kRowsPerLane],
+                                           float t0h, float t0l, const float (&nab)[kMultiTheta],
+                                           const float (&nbb)[kMultiTheta], const float (&nae)[kMultiTheta],
+                                           const float (&nbe)[kMultiTheta], float (&s)[2 * kMultiTheta][kRowsPerLane],
+                                           float* __restrict__ comp, float* __restrict__ colw, int lane)
+{
+    constexpr int R = kRowsPerLane;
+    constexpr int KT = kMultiTheta;
+    for (int ch = 0; ch < kTile; ch += kChunk) {
+        float p[2 * KT][R];
+#pragma unroll
+        for (int k = 0; k < 2 * KT; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r) p[k][r] = 0.0f;
+#pragma unroll 1
+        for (int g = ch; g < ch + kChunk; g += 4) {
+            float cp[KT][4];
+#pragma unroll
+            for (int q = 0; q < KT; ++q)
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) cp[q][cc] = 0.0f;
+#pragma unroll
+            for (int cc = 0; cc < 4; ++cc) {
+                const float4 hi = sj[2 * (g + cc)];
+                const float4 lo = sj[2 * (g + cc) + 1];
+                const float tj = (hi.z - t0h) + (lo.z - t0l);
+                const int j = j0 + g + cc;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const float dx = (xh[r] - hi.x) + (xl[r] - lo.x);
+                    const float dy = (yh[r] - hi.y) + (yl[r] - lo.y);
+                    const float dt = ti[r] - tj;
+                    const float r2 = fmaf(dx, dx, dy * dy);
+                    const float dt2 = dt * dt;
+                    const bool below = MODE != kDiag || j < lrow0 + r;
+                    const bool causal = MODE == kFullLow || j < ct[r];
+#pragma unroll
+                    for (int q = 0; q < KT; ++q) {
+                        float ab = fmaf(r2, nab[q], dt2 * nbb[q]);
+                        if (MODE == kDiag) ab = below ? ab : -INFINITY;
+                        const float b = __builtin_amdgcn_exp2f(ab);
+                        p[2 * q][r] += b;
+                        cp[q][cc] += b;
+                        float ae = fmaf(r2, nae[q], dt * nbe[q]);
+                        if (MODE != kFullLow) ae = causal ? ae : -INFINITY;
+                        p[2 * q + 1][r] += __builtin_amdgcn_exp2f(ae);
+                    }
+                }
+            }
+            float v[KT];
+            reduce4_multi<KT>(cp, v);
+            if ((lane & 15) == 0)
+#pragma unroll
+                for (int q = 0; q < KT; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
+        }
+#pragma unroll
+        for (int k = 0; k < 2 * KT; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r) two_sum_into(s[k][r], comp[(k * R + r) * kThreads], p[k][r]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void pair_multi_fp32c(const MultiReq rq)
+{
+    constexpr int R = kRowsPerLane;
+    constexpr int KT = kMultiTheta;
+    constexpr int K = 2 * KT;
+    constexpr int TB = kRowsPerBlock / kTile;
+    __shared__ float4 sj[2 * kTile];
+    __shared__ float colred[4][KT][kTile];
+    __shared__ float comp_lds[K * R * kThreads];
+    float* comp = comp_lds + threadIdx.x;
+
+    const int blk = (int)blockIdx.x;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int n = rq.n;
+    long long u = (long long)blk * rq.upb;
+    const long long uend = min(u + (long long)rq.upb, rq.units);
+    int I = sym_row_block(u);
+    int tile = (int)(u - sym_unit0(I));
+
+    float nab[KT], nbb[KT], nae[KT], nbe[KT];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) {
+        nab[q] = in_vgpr(rq.nab[q]);
+        nbb[q] = in_vgpr(rq.nbb[q]);
+        nae[q] = in_vgpr(rq.nae[q]);
+        nbe[q] = in_vgpr(rq.nbe[q]);
+    }
+    float xh[R], yh[R], xl[R], yl[R], ti[R];
+    int ct[R];
+    float t0h = 0.0f, t0l = 0.0f;
+    float s[K][R];
+    int cur = -1, w0 = 0, lrow0 = 0, clo = 0;
+    bool active = false;
+
+    for (; u < uend; ++u) {
+        if (I != cur) {
+            if (cur >= 0) {
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int r = 0; r < R; ++r)
+                        rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
+                            (double)s[k][r] + (double)comp[(k * R + r) * kThreads];
+            }
+            cur = I;
+            w0 = I * kRowsPerBlock + wave * (64 * R);
+            lrow0 = w0 + R * lane;
+            active = w0 < n;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = lrow0 + r;
+                const float4 a = rq.ev32[2 * (size_t)i];
+                const float4 b = rq.ev32[2 * (size_t)i + 1];
+                if (r == 0) {
+                    t0h = a.z;
+                    t0l = b.z;
+                }
+                xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
+                ti[r] = (a.z - t0h) + (b.z - t0l);
+                ct[r] = rq.cut[i];
+            }
+            clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    s[k][r] = 0.0f;
+                    comp[(k * R + r) * kThreads] = 0.0f;
+                }
+        }
+        const int j0 = tile * kTile;
+        __syncthreads();
+        const float4* src = rq.ev32 + 2 * (size_t)(j0 + threadIdx.x);
+        sj[2 * threadIdx.x] = src[0];
+        sj[2 * threadIdx.x + 1] = src[1];
+        __syncthreads();
+        int mode;
+        if (!active || j0 >= w0 + 64 * R) mode = kSkip;
+        else if (j0 + kTile <= w0) mode = (j0 + kTile <= clo) ? kFullLow : kMaskLow;
+        else mode = kDiag;
+        float* colw = &colred[wave][0][0];
+        if (mode == kSkip) {
+#pragma unroll
+            for (int q = 0; q < KT; ++q)
+#pragma unroll
+                for (int k4 = 0; k4 < 4; ++k4) colw[q * kTile + 4 * lane + k4] = 0.0f;
+        } else if (mode == kFullLow) {
+            multi_tile<kFullLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, lane);
+        } else if (mode == kMaskLow) {
+            multi_tile<kMaskLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, lane);
+        } else {
+            multi_tile<kDiag>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, lane);
+        }
+        __syncthreads();
+        const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;
+#pragma unroll
+        for (int q = 0; q < KT; ++q)
+            rq.colpart[q * rq.col_stride + cb] = (double)colred[0][q][threadIdx.x] + (double)colred[1][q][threadIdx.x] +
+                                                 (double)colred[2][q][threadIdx.x] + (double)colred[3][q][threadIdx.x];
+        if (++tile == TB * (I + 1)) {
+            tile = 0;
+            ++I;
+        }
+    }
+    if (cur >= 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
+                    (double)s[k][r] + (double)comp[(k * R + r) * kThreads];
+    }
+}
+
+__device__ __forceinline__ double normal_cdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
+
+// Per event and parameter vector: lambda, Lambda, ell_i and pi_i (binary64); block sums of ell.
+__global__ __launch_bounds__(kThreads) void epilogue_multi(const MultiEpi e)
+{
+    constexpr int KT = kMultiTheta;
+    constexpr long long TB = kRowsPerBlock / kTile;
+    __shared__ double red[KT][kThreads];
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    double v[KT] = {0, 0, 0, 0};
+    if (i < e.n) {
+        const int I = i / kRowsPerBlock, rho = i % kRowsPerBlock;
+        const long long bf = TB * I * (I + 1) / 2 / e.upb;
+        const long long bl = (TB * (I + 1) * (I + 2) / 2 - 1) / e.upb;
+        double Sb[KT] = {0, 0, 0, 0}, Se[KT] = {0, 0, 0, 0};
+        for (long long b = bf; b <= bl; ++b) {
+            const double* ps = e.part + (size_t)(b + I) * 2 * KT * kRowsPerBlock + rho;
+#pragma unroll
+            for (int q = 0; q < KT; ++q) {
+                Sb[q] += ps[(size_t)(2 * q) * kRowsPerBlock];
+                Se[q] += ps[(size_t)(2 * q + 1) * kRowsPerBlock];
+            }
+        }
+        for (int J = I; J < e.row_blocks; ++J) {
+            const double* pc = e.colpart + (long long)kRowsPerBlock * J * (J + 1) / 2 + i;
+#pragma unroll
+            for (int q = 0; q < KT; ++q) Sb[q] += pc[q * e.col_stride];
+        }
+        const double ti = e.ev64[i].z;
+        const double u = e.T - ti;
+#pragma unroll
+        for (int q = 0; q < KT; ++q) {
+            if (q >= e.nth) break;
+            const double lam = e.cb[q] * (Sb[q] + 1.0) + e.ce[q] * Se[q];
+            const double Lam = e.mu0[q] * (normal_cdf(u / e.tau_t[q]) - normal_cdf(-ti / e.tau_t[q])) -
+                               e.theta[q] * expm1(-e.omega[q] * u);
+            v[q] = log(lam) - Lam;
+            if (e.pi_out) e.pi_out[(size_t)q * e.n + i] = e.ce[q] * Se[q] / lam;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < KT; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int stride = kThreads / 2; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride)
+#pragma unroll
+            for (int q = 0; q < KT; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + stride];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < KT; ++q) e.block_part[(size_t)blockIdx.x * KT + q] = red[q][0];
+}
+
+__global__ __launch_bounds__(kThreads) void final_multi(const MultiEpi e)
+{
+    constexpr int KT = kMultiTheta;
+    __shared__ double red[KT][kThreads];
+    double v[KT] = {0, 0, 0, 0};
+    for (int b = threadIdx.x; b < e.nblocks; b += kThreads)
+#pragma unroll
+        for (int q = 0; q < KT; ++q) v[q] += e.block_part[(size_t)b * KT + q];
+#pragma unroll
+    for (int q = 0; q < KT; ++q) red[q][threadIdx.x] = v[q];
+    __syncthreads();
+    for (int stride = kThreads / 2; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride)
+#pragma unroll
+            for (int q = 0; q < KT; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + stride];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < KT; ++q) e.out[q] = red[q][0];
+}
+
+}  // namespace
+
+int multi_blocks_per_cu()
+{
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_multi_fp32c, kThreads, 0);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+// FP32C: kMultiTheta parameter vectors per pass.  Caller holds c->mu.
+static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_params* th, int S, double* out_ll,
+                                 double* out_pi)
+{
+    constexpr int KT = kMultiTheta;
+    const long long TB = kRowsPerBlock / kTile;
+    const long long T = d.npad / kRowsPerBlock;
+    const long long units = TB * T * (T + 1) / 2;
+    const long long slots = std::max(1, c->multi_slots);
+    const int upb = (int)std::max<long long>(1, (units + slots - 1) / slots);
+    const int items = (int)((units + upb - 1) / upb);
+    const long long col_stride = (long long)kRowsPerBlock * T * (T + 1) / 2;
+    const int nblocks = (int)((d.n + kThreads - 1) / kThreads);
+    const size_t part_d = (size_t)(items + T) * 2 * KT * kRowsPerBlock;
+    const size_t col_d = (size_t)KT * col_stride;
+    const size_t pi_d = out_pi ? (size_t)KT * d.n : 0;
+    const size_t need = (part_d + col_d + (size_t)nblocks * KT + 8 + pi_d) * sizeof(double);
+    hawkes_status st = reserve_blocking(c, need);
+    if (st != HAWKES_OK) return st;
+    double* base = (double*)c->blk.base;
+    MultiReq r;
+    memset(&r, 0, sizeof r);
+    r.ev32 = d.ev32;
+    r.cut = d.cut;
+    r.part = base;
+    r.colpart = base + part_d;
+    r.units = units;
+    r.col_stride = col_stride;
+    r.n = (int)d.n;
+    r.npad = d.npad;
+    r.row_blocks = (int)T;
+    r.upb = upb;
+    MultiEpi e;
+    memset(&e, 0, sizeof e);
+    e.ev64 = d.ev64;
+    e.part = r.part;
+    e.colpart = r.colpart;
+    e.block_part = base + part_d + col_d;
+    e.out = e.block_part + (size_t)nblocks * KT;
+    e.pi_out = out_pi ? e.out + 8 : nullptr;
+    e.col_stride = col_stride;
+    e.n = (int)d.n;
+    e.npad = d.npad;
+    e.row_blocks = (int)T;
+    e.upb = upb;
+    e.nblocks = nblocks;
+    e.T = d.T;
+    const double log2e = 1.44269504088896340736, two_pi = 6.28318530717958647693;
+    std::vector<double> host_out(8);
+    std::vector<double> host_pi(out_pi ? (size_t)KT * d.n : 0);
+    hipStream_t s = c->stream;
+    hipError_t err = hipStreamWaitEvent(s, c->blk_free, 0);
+    for (int s0 = 0; s0 < S && err == hipSuccess; s0 += KT) {
+        const int nth = std::min(KT, S - s0);
+        e.nth = nth;
+        for (int q = 0; q < KT; ++q) {
+            const hawkes_params& p = th[s0 + std::min(q, nth - 1)];  // pad with the last vector
+            r.nab[q] = (float)(-log2e / (2.0 * p.tau_x * p.tau_x));
+            r.nbb[q] = (float)(-log2e / (2.0 * p.tau_t * p.tau_t));
+            r.nae[q] = (float)(-log2e / (2.0 * p.h * p.h));
+            r.nbe[q] = (float)(-log2e * p.omega);
+            e.mu0[q] = p.mu0;
+            e.tau_t[q] = p.tau_t;
+            e.theta[q] = p.theta;
+            e.omega[q] = p.omega;
+            e.cb[q] = p.mu0 / (std::pow(two_pi, 1.5) * p.tau_x * p.tau_x * p.tau_t);
+            e.ce[q] = p.theta * p.omega / (two_pi * p.h * p.h);
+        }
+        pair_multi_fp32c<<<dim3(items), dim3(kThreads), 0, s>>>(r);
+        epilogue_multi<<<dim3(nblocks), dim3(kThreads), 0, s>>>(e);
+        final_multi<<<dim3(1), dim3(kThreads), 0, s>>>(e);
+        err = hipGetLastError();
+        if (err == hipSuccess) err = hipMemcpyAsync(host_out.data(), e.out, KT * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (err == hipSuccess && out_pi)
+            err = hipMemcpyAsync(host_pi.data(), e.pi_out, (size_t)KT * d.n * sizeof(double), hipMemcpyDeviceToHost, s);
+        if (err == hipSuccess) err = hipStreamSynchronize(s);
+        if (err != hipSuccess) break;
+        for (int q = 0; q < nth; ++q) {
+            if (out_ll) out_ll[s0 + q] = host_out[q];
+            if (out_pi)
+                for (int64_t k = 0; k < d.n; ++k) out_pi[(size_t)(s0 + q) * d.n + d.perm[k]] = host_pi[(size_t)q * d.n + k];
+        }
+    }
+    if (err == hipSuccess) err = hipEventRecord(c->blk_free, s);
+    if (err != hipSuccess) {
+        c->poisoned = true;
+        return hip_fail(err, "multi-parameter evaluation");
+    }
+    return HAWKES_OK;
+}
+
+}  // namespace hawkes
+
+using namespace hawkes;
+
+extern "C" hawkes_status hawkes_loglik_multi(hawkes_ctx* c, int32_t id, const hawkes_params* thetas, int32_t count,
+                                             int precision, double* out_loglik, double* out_pi)
+{
+    hawkes_status st = begin_call(c);
+    if (st != HAWKES_OK) return st;
+    if (count < 0 || (count > 0 && !thetas)) return fail(HAWKES_EINVAL, "bad parameter array");
+    if (!out_loglik && !out_pi) return fail(HAWKES_EINVAL, "no output requested");
+    if (precision != HAWKES_FP64 && precision != HAWKES_FP32C)
+        return fail(HAWKES_EINVAL, "precision %d is neither HAWKES_FP64 nor HAWKES_FP32C", precision);
+    for (int k = 0; k < count; ++k)
+        if ((st = check_params(&thetas[k])) != HAWKES_OK) return st;
+    if (count == 0) return HAWKES_OK;
+    if (precision == HAWKES_FP64) {
+        // One binary64 evaluation per parameter vector (per-event results give pi).
+        int64_t n = 0;
+        if ((st = hawkes_dataset_info(c, id, &n, nullptr)) != HAWKES_OK) return st;
+        std::vector<double> rows((size_t)n * kRowOut);
+        for (int k = 0; k < count; ++k) {
+            double o7[7];
+            if ((st = blocking_eval(c, id, &thetas[k], HAWKES_FP64, false, o7, rows.data())) != HAWKES_OK) return st;
+            if (out_loglik) out_loglik[k] = o7[0];
+            if (out_pi)
+                for (int64_t e = 0; e < n; ++e) out_pi[(size_t)k * n + e] = rows[(size_t)e * kRowOut + 3];
+        }
+        return HAWKES_OK;
+    }
+    std::lock_guard<std::mutex> lk(c->mu);
+    Dataset* d = find_dataset(c, id);
+    if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
+    return multi_fp32c(c, *d, thetas, count, out_loglik, out_pi);
+}

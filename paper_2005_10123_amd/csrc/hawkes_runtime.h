@@ -80,6 +80,7 @@ struct hawkes_ctx {
     hawkes::Server* server = nullptr;
     int scheme = hawkes::kSymmetric;  // how pair terms are enumerated (hawkes_set_pair_scheme)
     int sym_slots[2][2] = {{0, 0}, {0, 0}};  // [precision][grad] resident blocks of the symmetric kernel
+    int multi_slots = 0;                     // resident blocks of the multi-parameter kernel
 };
 
 namespace hawkes {
@@ -98,6 +99,12 @@ hawkes_status dev_alloc(hawkes_ctx* c, void** p, size_t bytes);
 void dev_free(hawkes_ctx* c, void* p, size_t bytes);
 Dataset* find_dataset(hawkes_ctx* c, int32_t id);
 void free_dataset(hawkes_ctx* c, Dataset& d);
+
+hawkes_status begin_call(hawkes_ctx* c);
+hawkes_status reserve_blocking(hawkes_ctx* c, size_t need);
+hawkes_status blocking_eval(hawkes_ctx* c, int32_t id, const hawkes_params* p, int precision, bool grad,
+                            double out7[7], double* host_rows);
+int multi_blocks_per_cu();
 
 hawkes_status server_start(hawkes_ctx* c);
 void server_stop(hawkes_ctx* c);

@@ -1,0 +1,167 @@
+"""Adaptive random-scan Metropolis-Hastings chains (the paper's Algorithm 1) driven by the batched
+serving API: every chain's likelihood evaluation is a request to ``hawkes_submit``, many chains are
+in flight at once, and a chain advances as soon as its own result is polled.
+
+Algorithm 1 (Section 2.2): pick a coordinate d uniformly; propose theta*_d from a normal centred at
+the current value with scale v_d, truncated to theta*_d > 0; accept with the Metropolis-Hastings
+ratio (prior x likelihood x the ratio of the truncated proposals' normalising constants); every
+b_d updates of coordinate d, multiply v_d by the acceptance proportion over 0.44 clamped to
+[0.5, 2], raise b_d to b_d^1.1 and reset the counters.  Because b_d^1.1 is not an integer, the
+interval ends when the counter reaches b_d or more.
+
+Priors (Section 2.1): truncated normals with lower bound 0 (half-normals) with standard deviation 1
+on mu0, 10 on theta, 10 on omega, and 10 on 1/h; tau_x and tau_t are held fixed.  The chain moves h
+itself, so the prior density of h carries the Jacobian |d(1/h)/dh| = 1/h^2 (a reading: the paper
+does not say on which scale the chain moves).
+
+Pure host logic: the log-likelihood comes from the library (or, in tests, from any callable).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# Coordinates of Theta = (mu0, tau_x, tau_t, theta, omega, h) that the chain updates.
+FREE = (0, 3, 4, 5)
+PRIOR_SD = {0: 1.0, 3: 10.0, 4: 10.0, 5: 10.0}
+
+
+def log_prior(theta) -> float:
+    """Half-normal priors of Section 2.1 (up to a constant); -inf outside the positive orthant."""
+    mu0, _, _, th, om, h = theta
+    if mu0 <= 0 or th <= 0 or om <= 0 or h <= 0:
+        return -math.inf
+    lp = -0.5 * (mu0 / PRIOR_SD[0]) ** 2 - 0.5 * (th / PRIOR_SD[3]) ** 2 - 0.5 * (om / PRIOR_SD[4]) ** 2
+    inv_h = 1.0 / h
+    lp += -0.5 * (inv_h / PRIOR_SD[5]) ** 2 - 2.0 * math.log(h)  # density of 1/h, moved to h
+    return lp
+
+
+def _log_norm_cdf(z: float) -> float:
+    return math.log(0.5 * math.erfc(-z / math.sqrt(2.0)))
+
+
+@dataclass
+class ChainState:
+    """One chain of Algorithm 1."""
+
+    theta: np.ndarray
+    rng: np.random.Generator
+    loglik: float = math.nan
+    b: np.ndarray = field(default_factory=lambda: np.full(6, 5.0))
+    l: np.ndarray = field(default_factory=lambda: np.zeros(6))
+    a: np.ndarray = field(default_factory=lambda: np.zeros(6))
+    v: np.ndarray = field(default_factory=lambda: np.ones(6))
+    proposal: np.ndarray | None = None
+    coord: int = -1
+    samples: list = field(default_factory=list)
+    accepted: int = 0
+    steps: int = 0
+
+    def propose(self) -> np.ndarray:
+        """Steps 3a-3b: choose d and draw theta*_d ~ Normal(theta_d, v_d) restricted to > 0."""
+        d = FREE[self.rng.integers(len(FREE))]
+        cur = self.theta[d]
+        while True:
+            x = cur + self.v[d] * self.rng.standard_normal()
+            if x > 0:
+                break
+        prop = self.theta.copy()
+        prop[d] = x
+        self.coord = d
+        self.proposal = prop
+        return prop
+
+    def log_ratio(self, loglik_prop: float) -> float:
+        """Step 4a in logs: target ratio times q(Theta | Theta*) / q(Theta* | Theta).  For normals
+        truncated at 0 the kernels' Gaussian parts cancel and the normalisers Phi(x / v) remain."""
+        d = self.coord
+        v = self.v[d]
+        x_old, x_new = self.theta[d], self.proposal[d]
+        lq = _log_norm_cdf(x_old / v) - _log_norm_cdf(x_new / v)
+        return (loglik_prop + log_prior(self.proposal)) - (self.loglik + log_prior(self.theta)) + lq
+
+    def accept_reject(self, loglik_prop: float):
+        """Steps 4b-4c (accept/reject) and 5 (adaptation)."""
+        d = self.coord
+        if math.log(self.rng.uniform()) < self.log_ratio(loglik_prop):
+            self.theta = self.proposal
+            self.loglik = loglik_prop
+            self.a[d] += 1
+            self.accepted += 1
+        self.l[d] += 1
+        if self.l[d] >= self.b[d]:
+            r3 = min(2.0, max(0.5, (self.a[d] / self.b[d]) / 0.44))
+            self.v[d] *= r3
+            self.b[d] = self.b[d] ** 1.1
+            self.l[d] = 0
+            self.a[d] = 0
+        self.proposal = None
+        self.steps += 1
+        self.samples.append(self.theta.copy())
+
+
+def run_local(loglik, theta0, steps: int, seed: int) -> ChainState:
+    """One chain with a synchronous log-likelihood callable (for tests and small runs)."""
+    ch = ChainState(np.array(theta0, float), np.random.default_rng(seed))
+    ch.loglik = loglik(ch.theta)
+    for _ in range(steps):
+        ch.accept_reject(loglik(ch.propose()))
+    return ch
+
+
+def run_served(ctx, chains: list, datasets: list, steps: int, precision="fp32c", poll_us=200):
+    """Advance many chains through the serving API until each has taken `steps` MH steps.
+
+    chains[k] runs on datasets[k].  Each chain keeps one request in flight; a chain's next proposal
+    is submitted as soon as its previous result is polled, so requests of different chains overlap
+    on the device.  Returns the number of requests served.
+    """
+    from . import binding
+
+    tag_of = {}
+    pending = []
+    for k, (ch, ds) in enumerate(zip(chains, datasets)):
+        tag_of[k] = ("init", k)
+        pending.append(binding.request(ds, ch.theta, precision, want_grad=False, tag=2 * k))
+    ctx.submit(pending)
+    waiting = len(chains)
+    served = 0
+    while waiting:
+        for r in ctx.poll(cap=512, timeout_us=poll_us):
+            served += 1
+            if r.status != 0:
+                raise RuntimeError(f"request {r.tag} failed with status {r.status}")
+            k, is_prop = divmod(int(r.tag), 2)
+            ch = chains[k]
+            if is_prop:
+                ch.accept_reject(r.loglik)
+            else:
+                ch.loglik = r.loglik
+            if ch.steps >= steps:
+                waiting -= 1
+                continue
+            ctx.submit([binding.request(datasets[k], ch.propose(), precision, want_grad=False, tag=2 * k + 1)])
+    return served
+
+
+def effective_sample_size(x: np.ndarray) -> float:
+    """ESS = n / tau with tau = 1 + 2 sum_k rho_k, the sum truncated at the first negative pair of
+    consecutive autocorrelations (Geyer's initial positive sequence)."""
+    x = np.asarray(x, float)
+    n = x.size
+    if n < 4 or np.var(x) == 0:
+        return float(n)
+    xc = x - x.mean()
+    f = np.fft.rfft(xc, 2 * n)
+    acf = np.fft.irfft(f * np.conj(f))[:n]
+    acf /= acf[0]
+    tau = -1.0
+    for m in range(0, n // 2):
+        pair = acf[2 * m] + acf[2 * m + 1]
+        if pair <= 0:
+            break
+        tau += 2.0 * pair
+    return n / max(1.0, tau)

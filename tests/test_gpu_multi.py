@@ -1,0 +1,48 @@
+"""Log-likelihood and self-excitation probabilities for many parameter vectors over one dataset
+(hawkes_loglik_multi) against the FP64 oracle, per parameter vector and per event."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2005_10123_amd import binding, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def thetas(S, seed):
+    rng = np.random.default_rng(seed)
+    return np.array(synth.THETA_CFG1) * np.exp(0.3 * rng.standard_normal((S, 6)))
+
+
+@pytest.mark.parametrize("n,S", [(1500, 7), (3000, 4), (700, 1), (4097, 5)])
+def test_multi_against_oracle(n, S):
+    x, y, t = synth.simulate(synth.SimSpec(n, 6.0, 400.0, 3, 0.5, 0.1, 0.4, (77, n, S)))
+    perm = np.random.default_rng(n).permutation(n)
+    x, y, t = x[perm], y[perm], t[perm]
+    th = thetas(S, n + S)
+    ctx = binding.Context(0)
+    ds = ctx.dataset(x, y, t)
+    for prec, tol in (("fp32c", 1e-5), ("fp64", 1e-10)):
+        ll, pi = ctx.loglik_multi(ds, th, prec)
+        for s in range(S):
+            ref = oracle.evaluate(x, y, t, th[s], rows=True)
+            assert abs(ll[s] - ref["ell"]) <= tol * abs(ref["ell"]), (prec, s, ll[s], ref["ell"])
+            assert np.max(np.abs(pi[s] - ref["row_pi"])) <= tol, (prec, s)
+        single = ctx.loglik(ds, th[-1], prec)
+        assert abs(single - ll[-1]) <= tol * abs(single)
+    only_ll = ctx.loglik_multi(ds, th, "fp32c", want_pi=False)
+    assert np.array_equal(only_ll, ctx.loglik_multi(ds, th, "fp32c")[0])
+    ds.close()
+    ctx.close()
+
+
+def test_multi_rejects_bad_parameters():
+    ctx = binding.Context(0)
+    ds = ctx.dataset(*synth.simulate(synth.SimSpec(300, 5.0, 100.0, 2, 0.5, 0.1, 0.3, (1, 1, 1))))
+    bad = thetas(3, 1)
+    bad[1, 5] = -1.0
+    with pytest.raises(binding.HawkesError) as e:
+        ctx.loglik_multi(ds, bad, "fp32c")
+    assert e.value.status == binding.HAWKES_EINVAL
+    ds.close()
+    ctx.close()
