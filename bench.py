@@ -160,6 +160,35 @@ def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed
             "sizes": [int(s) for s in sizes]}
 
 
+def pi_batch_run(ctx, n=55000, samples=64, seed=7):
+    """Self-excitation probabilities for many posterior-like parameter vectors (the paper evaluates
+    pi_n for 1,000 posterior samples over 55,000 events): the multi-parameter pass against one
+    single-parameter evaluation per vector."""
+    from paper_2005_10123_amd import synth
+    import torch
+
+    (x, y, t), _ = synth.config_events("city_85k_10km", n=n)
+    ds = ctx.dataset(x, y, t)
+    rng = np.random.default_rng(seed)
+    th = np.array(synth.THETA_CFG1) * np.exp(0.05 * rng.standard_normal((samples, 6)))
+    ctx.loglik_multi(ds, th[:4], "fp32c")  # warm-up
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    ll, pi = ctx.loglik_multi(ds, th, "fp32c")
+    multi_s = time.perf_counter() - a
+    k = 8
+    a = time.perf_counter()
+    for s in range(k):
+        ctx.rows(ds, th[s], "fp32c")
+    single_s = (time.perf_counter() - a) / k * samples
+    ds.close()
+    pairs = float(n) * n * samples
+    return {"n_events": n, "samples": samples, "seconds": multi_s, "theta_pairs_per_s": pairs / multi_s,
+            "seconds_per_1000_samples": multi_s / samples * 1000,
+            "one_vector_at_a_time_seconds": single_s, "speedup_vs_one_at_a_time": single_s / multi_s,
+            "mean_pi": float(pi.mean())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -246,6 +275,7 @@ def main():
     ds.close()
     if not args.no_serving:
         result["serving"] = serving_run(ctx, seconds=args.serving_seconds)
+        result["pi_batch"] = pi_batch_run(ctx)
     ctx.close()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(x, y, t, theta)
