@@ -165,3 +165,144 @@ def effective_sample_size(x: np.ndarray) -> float:
             break
         tau += 2.0 * pair
     return n / max(1.0, tau)
+
+
+# ----------------------------------------------------------------------------------------------
+# Hamiltonian Monte Carlo on q = log(Theta_free), using the fused log-likelihood gradient.
+#
+# The target in q is ell(Theta) + log prior(Theta) + sum_d q_d (Jacobian of Theta_d = exp(q_d)).
+# Leapfrog integration with a diagonal unit mass, a fixed number of steps, and a step size tuned
+# during warm-up by dual averaging (Hoffman and Gelman, 2014, Algorithm 5) towards a target mean
+# acceptance probability; frozen afterwards.
+
+def log_prior_grad(theta) -> np.ndarray:
+    """d log_prior / d Theta for the free coordinates (zeros elsewhere)."""
+    g = np.zeros(6)
+    g[0] = -theta[0] / PRIOR_SD[0] ** 2
+    g[3] = -theta[3] / PRIOR_SD[3] ** 2
+    g[4] = -theta[4] / PRIOR_SD[4] ** 2
+    h = theta[5]
+    g[5] = 1.0 / (h ** 3 * PRIOR_SD[5] ** 2) - 2.0 / h
+    return g
+
+
+@dataclass
+class HMCChain:
+    theta: np.ndarray
+    rng: np.random.Generator
+    leapfrog: int = 8
+    eps: float = 0.05
+    warmup: int = 100
+    target_accept: float = 0.75
+    samples: list = field(default_factory=list)
+    accepted: int = 0
+    iters: int = 0
+    evals: int = 0
+    # dual averaging state
+    _mu: float = 0.0
+    _hbar: float = 0.0
+    _log_eps_bar: float = 0.0
+
+    def __post_init__(self):
+        self._mu = math.log(10.0 * self.eps)
+
+    @staticmethod
+    def _q(theta):
+        return np.log(theta[list(FREE)])
+
+    def _theta(self, q):
+        th = self.theta.copy()
+        th[list(FREE)] = np.exp(q)
+        return th
+
+    def _logp_grad(self, theta, ell, grad):
+        """Target and its gradient in q from (ell, d ell / d Theta)."""
+        q = self._q(theta)
+        lp = ell + log_prior(theta) + float(q.sum())
+        g_theta = grad + log_prior_grad(theta)
+        gq = theta[list(FREE)] * g_theta[list(FREE)] + 1.0
+        return lp, gq
+
+    def run(self, iterations: int):
+        """Generator: yields a Theta to evaluate and receives (ell, grad) for it."""
+        ell, grad = yield self.theta.copy()
+        self.evals += 1
+        lp, gq = self._logp_grad(self.theta, ell, grad)
+        for it in range(iterations):
+            q0 = self._q(self.theta)
+            p0 = self.rng.standard_normal(q0.size)
+            q, p, g = q0.copy(), p0.copy(), gq.copy()
+            lp_new, ok = lp, True
+            theta_new = self.theta
+            for _ in range(self.leapfrog):
+                p = p + 0.5 * self.eps * g
+                q = q + self.eps * p
+                theta_new = self._theta(q)
+                free = theta_new[list(FREE)]
+                if not np.all(np.isfinite(free)) or np.any(free > 1e12) or np.any(free < 1e-12):
+                    ok = False  # left the region the likelihood accepts: a divergent trajectory
+                    break
+                ell_n, grad_n = yield theta_new
+                self.evals += 1
+                lp_new, g = self._logp_grad(theta_new, ell_n, grad_n)
+                if not (math.isfinite(lp_new) and np.all(np.isfinite(g))):
+                    ok = False
+                    break
+                p = p + 0.5 * self.eps * g
+            alpha = 0.0
+            if ok:
+                log_alpha = (lp_new - 0.5 * p @ p) - (lp - 0.5 * p0 @ p0)
+                if math.isfinite(log_alpha):
+                    alpha = 1.0 if log_alpha >= 0 else math.exp(log_alpha)
+            if self.rng.uniform() < alpha:
+                self.theta, lp, gq = theta_new, lp_new, g
+                self.accepted += 1
+            self.iters += 1
+            if it < self.warmup:
+                m = it + 1
+                t0, gamma, kappa = 10.0, 0.05, 0.75
+                self._hbar = (1 - 1 / (m + t0)) * self._hbar + (self.target_accept - alpha) / (m + t0)
+                log_eps = self._mu - math.sqrt(m) / gamma * self._hbar
+                w = m ** (-kappa)
+                self._log_eps_bar = w * log_eps + (1 - w) * self._log_eps_bar
+                self.eps = math.exp(log_eps)
+                if it == self.warmup - 1:
+                    self.eps = math.exp(self._log_eps_bar)
+            else:
+                self.samples.append(self.theta.copy())
+
+
+def run_hmc_local(loglik_grad, theta0, iterations: int, seed: int, **kw) -> HMCChain:
+    """One HMC chain with a synchronous (ell, grad) callable."""
+    ch = HMCChain(np.array(theta0, float), np.random.default_rng(seed), **kw)
+    gen = ch.run(iterations)
+    th = next(gen)
+    try:
+        while True:
+            th = gen.send(loglik_grad(th))
+    except StopIteration:
+        pass
+    return ch
+
+
+def run_hmc_served(ctx, chains: list, datasets: list, iterations: int, precision="fp32c", poll_us=200):
+    """Advance HMC chains through the serving API (one gradient request in flight per chain)."""
+    from . import binding
+
+    gens = [ch.run(iterations) for ch in chains]
+    ctx.submit([binding.request(datasets[k], next(g), precision, want_grad=True, tag=k) for k, g in enumerate(gens)])
+    live = len(chains)
+    served = 0
+    while live:
+        for r in ctx.poll(cap=512, timeout_us=poll_us):
+            served += 1
+            if r.status != 0:
+                raise RuntimeError(f"request {r.tag} failed with status {r.status}")
+            k = int(r.tag)
+            try:
+                th = gens[k].send((r.loglik, np.array(r.grad[:])))
+            except StopIteration:
+                live -= 1
+                continue
+            ctx.submit([binding.request(datasets[k], th, precision, want_grad=True, tag=k)])
+    return served

@@ -80,3 +80,34 @@ def test_ess_of_iid_and_ar1():
         x[k] = 0.9 * x[k - 1] + rng.standard_normal()
     ess = mcmc.effective_sample_size(x)
     assert 20000 * 0.03 < ess < 20000 * 0.08  # (1 - 0.9) / (1 + 0.9) = 0.053
+
+
+def loglik_grad(theta):
+    """(ell, d ell / d Theta) with the gamma-product posterior of the MH test."""
+    g = -mcmc.log_prior_grad(theta)
+    for d in mcmc.FREE:
+        k, s, x = SHAPE[d], SCALE[d], theta[d]
+        g[d] += (k - 1) / x - 1 / s
+    return loglik(theta), g
+
+
+def test_log_prior_grad_matches_finite_differences():
+    th = np.array([0.7, 0.5, 20.0, 0.2, 1.3, 0.12])
+    g = mcmc.log_prior_grad(th)
+    for d in mcmc.FREE:
+        e = np.zeros(6)
+        e[d] = 1e-6 * th[d]
+        fd = (mcmc.log_prior(th + e) - mcmc.log_prior(th - e)) / (2 * e[d])
+        assert abs(fd - g[d]) <= 1e-6 * max(1.0, abs(g[d]))
+
+
+def test_hmc_recovers_known_posterior():
+    theta0 = np.array([1.0, 0.5, 20.0, 0.3, 0.5, 0.1])
+    ch = mcmc.run_hmc_local(loglik_grad, theta0, 4000, seed=5, warmup=300)
+    samples = np.array(ch.samples)
+    for d in mcmc.FREE:
+        x = samples[:, d]
+        ess = mcmc.effective_sample_size(x)
+        mean, sd = SHAPE[d] * SCALE[d], math.sqrt(SHAPE[d]) * SCALE[d]
+        assert abs(x.mean() - mean) < 4.5 * sd / math.sqrt(ess), (d, x.mean(), mean, ess)
+    assert 0.5 < ch.accepted / ch.iters < 0.95
