@@ -44,6 +44,7 @@ struct PairReq {
     const int* cut;
     double* part;         // direct: [splits][K][npad]; symmetric: [blocks + row_blocks][K][kRowsPerBlock]
     double* colpart;      // symmetric: [KC][col_stride] column sums of row block I at RB*I(I+1)/2 + j
+                          // (binary32 values in the FP32C pass)
     long long units;      // symmetric: row_blocks (row_blocks + 1) / 2 * (kRowsPerBlock / kTile)
     long long col_stride; // symmetric: kRowsPerBlock * row_blocks (row_blocks + 1) / 2
     int n, npad;
@@ -68,8 +69,9 @@ struct PairBatch {
 struct EpiReq {
     const double4* ev64;
     const double* part;
-    const double* colpart;  // symmetric scheme only
+    const double* colpart;  // symmetric scheme only (binary32 values when colpart_f32)
     long long col_stride;
+    int colpart_f32;
     double* rows_out;     // [n][kRowOut] in sorted order, or nullptr
     double* block_part;   // [nblocks][7]
     double* out7;         // 7 doubles: ell, gradient

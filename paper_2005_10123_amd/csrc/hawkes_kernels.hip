@@ -472,12 +472,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
             sym_tile_fp32<kDiag, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, lane);
         }
         __syncthreads();
-        // Column totals of this tile over the block's four waves, in wave order.
+        // Column totals of this tile over the block's four waves, in wave order (binary32: each
+        // is a sum of binary32 terms; the epilogue adds them over row blocks in binary64).
         const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;
+        float* colpart32 = reinterpret_cast<float*>(rq.colpart);
 #pragma unroll
         for (int qq = 0; qq < KC; ++qq)
-            rq.colpart[qq * rq.col_stride + cb] = (double)colred[0][qq][threadIdx.x] + (double)colred[1][qq][threadIdx.x] +
-                                                  (double)colred[2][qq][threadIdx.x] + (double)colred[3][qq][threadIdx.x];
+            colpart32[qq * rq.col_stride + cb] = (float)((double)colred[0][qq][threadIdx.x] + (double)colred[1][qq][threadIdx.x] +
+                                                         (double)colred[2][qq][threadIdx.x] + (double)colred[3][qq][threadIdx.x]);
         if (++tile == TB * (I + 1)) {
             tile = 0;
             ++I;
@@ -696,14 +698,28 @@ __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
                     S[3] += ps[kRowsPerBlock];
                 }
             }
-            // Column sums: the background terms with every later event, by row block.
-            for (int J = I; J < rq.row_blocks; ++J) {
-                const double* pc = rq.colpart + (long long)kRowsPerBlock * J * (J + 1) / 2 + i;
-                S[0] += pc[0];
-                if (rq.grad) {
-                    S[1] += pc[rq.col_stride];
-                    S[2] += pc[2 * rq.col_stride];
+            // Column sums: the background terms with every later event, by row block, gathered
+            // four row blocks at a time into four partial sums combined in a fixed order (keeps
+            // four independent loads in flight per event).
+            const int KC = rq.grad ? 3 : 1;
+            for (int q = 0; q < KC; ++q) {
+                double acc[4] = {0, 0, 0, 0};
+                const long long off = q * rq.col_stride + i;
+                int J = I;
+                if (rq.colpart_f32) {
+                    const float* pc = reinterpret_cast<const float*>(rq.colpart) + off;
+                    for (; J + 3 < rq.row_blocks; J += 4)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[u] += pc[(long long)kRowsPerBlock * (J + u) * (J + u + 1) / 2];
+                    for (; J < rq.row_blocks; ++J) acc[0] += pc[(long long)kRowsPerBlock * J * (J + 1) / 2];
+                } else {
+                    const double* pc = rq.colpart + off;
+                    for (; J + 3 < rq.row_blocks; J += 4)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[u] += pc[(long long)kRowsPerBlock * (J + u) * (J + u + 1) / 2];
+                    for (; J < rq.row_blocks; ++J) acc[0] += pc[(long long)kRowsPerBlock * J * (J + 1) / 2];
                 }
+                S[q] += (acc[0] + acc[1]) + (acc[2] + acc[3]);
             }
             S[0] += 1.0;  // the diagonal term B_ii = 1
         } else {

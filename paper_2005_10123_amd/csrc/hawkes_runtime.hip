@@ -105,6 +105,7 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
     e.part = cv.part;
     e.colpart = cv.colpart;
     e.col_stride = pl.col_stride;
+    e.colpart_f32 = (pl.scheme == kSymmetric && precision == kFP32C) ? 1 : 0;
     e.block_part = cv.block_part;
     e.out7 = cv.out7;
     e.rows_out = cv.rows;
