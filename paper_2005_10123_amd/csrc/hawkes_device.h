@@ -8,6 +8,10 @@
 namespace hawkes {
 namespace dev {
 
+// A float in LDS, addressed as such (accesses through it stay LDS instructions even when the
+// pointer is volatile).
+using lds_float = __attribute__((address_space(3))) float;
+
 constexpr int kChunk = 64;  // pair terms summed plainly in binary32 before a compensated merge
 
 enum Mode : int { kNone = 0, kFull = 1, kMask = 2 };
@@ -32,44 +36,33 @@ __device__ __forceinline__ void two_sum_into(float& s, float& c, float p)
 }
 
 // 2^a in binary64 for a <= 0 (a = -inf allowed).  Range reduction a = k + f, k = rint(a),
-// |f| <= 1/2, then 2^f = exp(f ln 2) by its Taylor polynomial of degree 12 (truncation error
-// below 2e-16 relative on |f ln 2| <= 0.347), scaled by 2^k.  Arguments below -1100 give exactly 0.
+// |f| <= 1/2, then 2^f by the degree-11 polynomial that minimises the maximal relative error on
+// [-1/2, 1/2] (Remez exchange, exp2_minimax.py; 3.4e-17 relative with the coefficients rounded to
+// binary64, below the rounding of the Horner evaluation), scaled by 2^k.  Arguments below -1100
+// give exactly 0.
 __device__ __forceinline__ double exp2_f64(double a)
 {
     a = fmax(a, -1100.0);
     const double k = rint(a);
     const double f = a - k;
-    double p = 2.5678435993488205142e-11;
-    p = fma(p, f, 4.4455382718708114976e-10);
-    p = fma(p, f, 7.0549116208011233299e-09);
-    p = fma(p, f, 1.0178086009239699727e-07);
-    p = fma(p, f, 1.3215486790144309488e-06);
-    p = fma(p, f, 1.5252733804059840280e-05);
-    p = fma(p, f, 1.5403530393381609954e-04);
-    p = fma(p, f, 1.3333558146428443423e-03);
-    p = fma(p, f, 9.6181291076284771620e-03);
-    p = fma(p, f, 5.5504108664821579953e-02);
-    p = fma(p, f, 2.4022650695910071233e-01);
-    p = fma(p, f, 6.9314718055994530942e-01);
+    double p = 4.43138940123033412484e-10;
+    p = fma(p, f, 7.07390645602150607471e-09);
+    p = fma(p, f, 1.01782190361934708864e-07);
+    p = fma(p, f, 1.32154346232020881375e-06);
+    p = fma(p, f, 1.52527334528178733073e-05);
+    p = fma(p, f, 1.54035304585322497346e-04);
+    p = fma(p, f, 1.33335581468151023049e-03);
+    p = fma(p, f, 9.61812910759227840396e-03);
+    p = fma(p, f, 5.55041086648198483955e-02);
+    p = fma(p, f, 2.40226506959101443472e-01);
+    p = fma(p, f, 6.93147180559945286227e-01);
     p = fma(p, f, 1.0);
     return ldexp(p, (int)k);
 }
 
 enum SymMode : int { kSkip = 0, kFullLow = 1, kMaskLow = 2, kDiag = 3 };
 
-// v_permlane32_swap exchanges the upper 32 lanes of the first register with the lower 32 lanes
-// of the second; v_permlane16_swap exchanges the odd 16-lane rows of the first with the even rows
-// of the second.  Written as inline assembly with both registers as outputs (the compiler
-// builtin's second result is not reliable); the s_nop covers the hazard of a VALU write
-// immediately followed by a permlane read of the same register.
-__device__ __forceinline__ void swap32(float& a, float& b)
-{
-    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
-}
-__device__ __forceinline__ void swap16(float& a, float& b)
-{
-    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
-}
+// Lane-rotated copy of v within each 16-lane row (DPP control CTRL, e.g. 0x128 = row_ror:8).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)
 {
@@ -84,87 +77,72 @@ __device__ __forceinline__ double dpp_d(double v)
     r.y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)u.y, CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, r);
 }
-__device__ __forceinline__ void swap32(double& a, double& b)
-{
-    uint2 ua = __builtin_bit_cast(uint2, a), ub = __builtin_bit_cast(uint2, b);
-    asm("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\tv_permlane32_swap_b32 %2, %3"
-        : "+v"(ua.x), "+v"(ub.x), "+v"(ua.y), "+v"(ub.y));
-    a = __builtin_bit_cast(double, ua);
-    b = __builtin_bit_cast(double, ub);
-}
-__device__ __forceinline__ void swap16(double& a, double& b)
-{
-    uint2 ua = __builtin_bit_cast(uint2, a), ub = __builtin_bit_cast(uint2, b);
-    asm("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\tv_permlane16_swap_b32 %2, %3"
-        : "+v"(ua.x), "+v"(ub.x), "+v"(ua.y), "+v"(ub.y));
-    a = __builtin_bit_cast(double, ua);
-    b = __builtin_bit_cast(double, ub);
-}
 
-// Sum over the 64 lanes of v0..v3 (four columns); lane l receives the total of column l / 16.
-// The swaps pair lane l with l + 32 (then l + 16) while handing half of the columns to each side,
-// so the two exchange steps cost one add per column pair; rotations by 8, 4, 2, 1 within each
-// 16-lane row finish the sum.  10 operations per four columns.
-template <typename T>
-__device__ __forceinline__ T reduce4(T v0, T v1, T v2, T v3)
+// Column sums of one group of four columns over the 64 lanes of a wave, through a wave-private
+// LDS area `red` of 4 x 64 values: each lane stores its partial sums of the four columns, reads
+// back the values of four consecutive lanes of one column (lane l: column l / 16), adds them,
+// and a rotation tree over the 16 lanes of its DPP row finishes the sum, so every lane of row c
+// holds the total of column c.  One quantity at a time; out[q] is valid in every lane.  Cheaper
+// on the VALU than an all-register transposing tree, whose cross-half lane exchanges
+// (v_permlane32/16_swap) issue at half rate.  LDS operations of one wave complete in order, so
+// the area is reused without waits.
+template <int KC, int NQ>
+__device__ __forceinline__ void column_sums4(const float (&cp)[NQ][4], float* __restrict__ red, int lane, float (&out)[NQ])
 {
-    swap32(v0, v2);
-    swap32(v1, v3);
-    T a0 = v0 + v2, a1 = v1 + v3;
-    swap16(a0, a1);
-    T z = a0 + a1;
-    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) red[cc * 64 + lane] = cp[q][cc];
+        __builtin_amdgcn_wave_barrier();
+        const float4 v = *reinterpret_cast<const float4*>(red + (lane >> 4) * 64 + (lane & 15) * 4);
+        __builtin_amdgcn_wave_barrier();
+        float z = (v.x + v.y) + (v.z + v.w);
         z += dpp_f<0x128>(z);  // row_ror:8
         z += dpp_f<0x124>(z);  // row_ror:4
         z += dpp_f<0x122>(z);  // row_ror:2
         z += dpp_f<0x121>(z);  // row_ror:1
-    } else {
+        out[q] = z;
+    }
+}
+
+template <int KC, int NQ>
+__device__ __forceinline__ void column_sums4(const double (&cp)[NQ][4], double* __restrict__ red, int lane, double (&out)[NQ])
+{
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+#pragma unroll
+        for (int cc = 0; cc < 4; ++cc) red[cc * 64 + lane] = cp[q][cc];
+        __builtin_amdgcn_wave_barrier();
+        const double* src = red + (lane >> 4) * 64 + (lane & 15) * 4;
+        const double2 v0 = *reinterpret_cast<const double2*>(src);
+        const double2 v1 = *reinterpret_cast<const double2*>(src + 2);
+        __builtin_amdgcn_wave_barrier();
+        double z = (v0.x + v0.y) + (v1.x + v1.y);
         z += dpp_d<0x128>(z);
         z += dpp_d<0x124>(z);
         z += dpp_d<0x122>(z);
         z += dpp_d<0x121>(z);
+        out[q] = z;
     }
-    return z;
 }
 
-// reduce4 for KC quantities at once, step by step interleaved so that each dependent DPP step
-// of one quantity is separated by the others' (hides the DPP read-after-write wait states).
-template <int KC, int NQ, typename T>
-__device__ __forceinline__ void reduce4_multi(T (&cp)[NQ][4], T (&out)[NQ])
+// Wave priority from a block's progress through its range of work units.  The hardware issues
+// from the oldest ready wave first, so blocks with equal work that share a CU finish far apart
+// and the CU runs its last block alone, at one wave per SIMD, which cannot keep the VALU busy.
+// Blocks that are behind issue first instead: level 3 below 70 % of the range, then 2, 1 and 0
+// from 70, 85 and 95 %.  `level` is the wave's current level (-1 before the first call); every
+// argument is uniform over the block.
+__device__ __forceinline__ void progress_priority(long long done, long long total, int& level)
 {
-    T a0[KC], a1[KC];
-#pragma unroll
-    for (int q = 0; q < KC; ++q) {
-        swap32(cp[q][0], cp[q][2]);
-        swap32(cp[q][1], cp[q][3]);
-    }
-#pragma unroll
-    for (int q = 0; q < KC; ++q) {
-        a0[q] = cp[q][0] + cp[q][2];
-        a1[q] = cp[q][1] + cp[q][3];
-    }
-#pragma unroll
-    for (int q = 0; q < KC; ++q) swap16(a0[q], a1[q]);
-#pragma unroll
-    for (int q = 0; q < KC; ++q) out[q] = a0[q] + a1[q];
-    if constexpr (sizeof(T) == 4) {
-#pragma unroll
-        for (int q = 0; q < KC; ++q) out[q] += dpp_f<0x128>(out[q]);
-#pragma unroll
-        for (int q = 0; q < KC; ++q) out[q] += dpp_f<0x124>(out[q]);
-#pragma unroll
-        for (int q = 0; q < KC; ++q) out[q] += dpp_f<0x122>(out[q]);
-#pragma unroll
-        for (int q = 0; q < KC; ++q) out[q] += dpp_f<0x121>(out[q]);
-    } else {
-#pragma unroll
-        for (int q = 0; q < KC; ++q) out[q] += dpp_d<0x128>(out[q]);
-#pragma unroll
-        for (int q = 0; q < KC; ++q) out[q] += dpp_d<0x124>(out[q]);
-#pragma unroll
-        for (int q = 0; q < KC; ++q) out[q] += dpp_d<0x122>(out[q]);
-#pragma unroll
-        for (int q = 0; q < KC; ++q) out[q] += dpp_d<0x121>(out[q]);
+    const long long d = 20 * done;
+    const int want = d >= 19 * total ? 0 : d >= 17 * total ? 1 : d >= 14 * total ? 2 : 3;
+    if (want == level) return;
+    level = want;
+    switch (want) {
+    case 0: __builtin_amdgcn_s_setprio(0); break;
+    case 1: __builtin_amdgcn_s_setprio(1); break;
+    case 2: __builtin_amdgcn_s_setprio(2); break;
+    default: __builtin_amdgcn_s_setprio(3); break;
     }
 }
 

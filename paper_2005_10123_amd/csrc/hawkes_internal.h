@@ -53,6 +53,7 @@ struct PairReq {
     int tiles_per_split;  // direct: kTile-event tiles in each column range
     int upb;              // symmetric: work units per block
     int item_begin;       // first work item (block) of this request in the launch
+    int balance;          // symmetric: 1 when the launch has the device to itself (progress priority)
     // Negated base-2 exponent coefficients: B = 2^(nab r^2 + nbb dt^2), E = 2^(nae r^2 + nbe dt).
     // The FP32C pass works in scaled time dt' = ts dt with ts = tsh + tsl = sqrt(-nbb):
     // B = 2^(nab r^2 - dt'^2), E = 2^(nae r^2 + kte dt') with kte = nbe / ts.

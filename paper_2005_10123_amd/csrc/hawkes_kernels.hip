@@ -300,16 +300,15 @@ __global__ __launch_bounds__(kThreads) void pair_fp64(const PairBatch batch)
 // mask for B; tiles straddling them mask j >= i; tiles above are skipped.
 
 // One tile of the FP32C symmetric pass for one wave.
-template <int MODE, bool GRAD>
+template <int MODE, bool GRAD, int R, int NT>
 __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int j0, int lrow0,
-                                              const float (&xh)[kRowsPerLane], const float (&yh)[kRowsPerLane],
-                                              const float (&xl)[kRowsPerLane], const float (&yl)[kRowsPerLane],
-                                              const float (&ti)[kRowsPerLane], const int (&ct)[kRowsPerLane],
+                                              const float (&xh)[R], const float (&yh)[R],
+                                              const float (&xl)[R], const float (&yl)[R],
+                                              const float (&ti)[R], const int (&ct)[R],
                                               float t0h, float t0l, float tsh, float tsl, float nab, float nae,
-                                              float kte, float (&s)[6][kRowsPerLane], float* __restrict__ comp,
-                                              float* __restrict__ colw, int lane)
+                                              float kte, float (&s)[6][R], volatile lds_float* comp,
+                                              float* __restrict__ colw, float* __restrict__ red, int lane)
 {
-    constexpr int R = kRowsPerLane;
     constexpr int K = GRAD ? 6 : 2;
     constexpr int KC = GRAD ? 3 : 1;
     for (int ch = 0; ch < kTile; ch += kChunk) {
@@ -362,7 +361,7 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
                 }
             }
             float v[3];
-            reduce4_multi<KC>(cp, v);
+            column_sums4<KC>(cp, red, lane, v);
             if ((lane & 15) == 0)
 #pragma unroll
                 for (int q = 0; q < KC; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
@@ -371,26 +370,35 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float& cc = comp[(k * R + r) * kThreads];
+                float cc = comp[(k * R + r) * NT];
                 two_sum_into(s[k][r], cc, p[k][r]);
+                comp[(k * R + r) * NT] = cc;
             }
     }
 }
 
+// Shape of the FP32C symmetric pass: kSymRows rows per lane; a block's threads together hold one
+// row block of the walk.
+constexpr int kSymRows = 4;
+constexpr int kSymThreads = kRowsPerBlock / kSymRows;
+constexpr int kSymWaves = kSymThreads / 64;
+static_assert(kSymThreads % 64 == 0 && kTile % kSymThreads == 0, "symmetric FP32C block shape");
+
 // The compensation terms of the row sums are touched once per 64 columns, so they live in LDS
-// (one float per thread per accumulator, thread-contiguous) rather than in registers; that keeps
-// the kernel within the register budget of three waves per SIMD.
+// (one float per thread per accumulator, thread-contiguous) rather than in registers.
 template <bool GRAD>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) void pair_sym_fp32c(const PairBatch batch)
+__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSymRows == 4 ? 3 : 2))) void pair_sym_fp32c(const PairBatch batch)
 {
-    constexpr int R = kRowsPerLane;
+    constexpr int R = kSymRows;
+    constexpr int NT = kSymThreads;
     constexpr int K = GRAD ? 6 : 2;
     constexpr int KC = GRAD ? 3 : 1;
     constexpr int TB = kRowsPerBlock / kTile;
     __shared__ float4 sj[2 * kTile];
-    __shared__ float colred[4][KC][kTile];
-    __shared__ float comp_lds[K * R * kThreads];
-    float* comp = comp_lds + threadIdx.x;
+    __shared__ float colred[kSymWaves][KC][kTile];
+    __shared__ float comp_lds[K * R * NT];
+    __shared__ float red_lds[kSymWaves][4 * 64];
+    volatile lds_float* comp = (lds_float*)comp_lds + threadIdx.x;
 
     const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
     const PairReq& rq = batch.r[q];
@@ -400,6 +408,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     const int n = rq.n;
     long long u = (long long)blk * rq.upb;
     const long long uend = min(u + (long long)rq.upb, rq.units);
+    const long long ubeg = u;
+    int prio = -1;
     int I = sym_row_block(u);
     int tile = (int)(u - sym_unit0(I));
 
@@ -413,6 +423,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
     bool active = false;
 
     for (; u < uend; ++u) {
+        if (rq.balance) progress_priority(u - ubeg, uend - ubeg, prio);
         if (I != cur) {
             if (cur >= 0) {
 #pragma unroll
@@ -420,7 +431,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
                     for (int r = 0; r < R; ++r)
                         rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
-                            (double)s[k][r] + (double)comp[(k * R + r) * kThreads];
+                            (double)s[k][r] + (double)comp[(k * R + r) * NT];
             }
             cur = I;
             w0 = I * kRowsPerBlock + wave * (64 * R);
@@ -446,13 +457,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
                 for (int r = 0; r < R; ++r) s[k][r] = 0.0f;
 #pragma unroll
-            for (int k = 0; k < K * R; ++k) comp[k * kThreads] = 0.0f;
+            for (int k = 0; k < K * R; ++k) comp[k * NT] = 0.0f;
         }
         const int j0 = tile * kTile;
         __syncthreads();
-        const float4* src = rq.ev32 + 2 * (size_t)(j0 + threadIdx.x);
-        sj[2 * threadIdx.x] = src[0];
-        sj[2 * threadIdx.x + 1] = src[1];
+#pragma unroll
+        for (int c = threadIdx.x; c < kTile; c += NT) {
+            const float4* src = rq.ev32 + 2 * (size_t)(j0 + c);
+            sj[2 * c] = src[0];
+            sj[2 * c + 1] = src[1];
+        }
         __syncthreads();
         int mode;
         if (!active || j0 >= w0 + 64 * R) mode = kSkip;
@@ -465,21 +479,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
         } else if (mode == kFullLow) {
-            sym_tile_fp32<kFullLow, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, lane);
+            sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
         } else if (mode == kMaskLow) {
-            sym_tile_fp32<kMaskLow, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, lane);
+            sym_tile_fp32<kMaskLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
         } else {
-            sym_tile_fp32<kDiag, GRAD>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, lane);
+            sym_tile_fp32<kDiag, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
         }
         __syncthreads();
-        // Column totals of this tile over the block's four waves, in wave order (binary32: each
-        // is a sum of binary32 terms; the epilogue adds them over row blocks in binary64).
-        const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;
+        // Column totals of this tile over the block's waves, in wave order (binary32: each is a
+        // sum of binary32 terms; the epilogue adds them over row blocks in binary64).
         float* colpart32 = reinterpret_cast<float*>(rq.colpart);
 #pragma unroll
-        for (int qq = 0; qq < KC; ++qq)
-            colpart32[qq * rq.col_stride + cb] = (float)((double)colred[0][qq][threadIdx.x] + (double)colred[1][qq][threadIdx.x] +
-                                                         (double)colred[2][qq][threadIdx.x] + (double)colred[3][qq][threadIdx.x]);
+        for (int c = threadIdx.x; c < kTile; c += NT) {
+            const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + c;
+#pragma unroll
+            for (int qq = 0; qq < KC; ++qq) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < kSymWaves; ++w) v += (double)colred[w][qq][c];
+                colpart32[qq * rq.col_stride + cb] = (float)v;
+            }
+        }
         if (++tile == TB * (I + 1)) {
             tile = 0;
             ++I;
@@ -491,7 +511,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(3))) v
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
-                    (double)s[k][r] + (double)comp[(k * R + r) * kThreads];
+                    (double)s[k][r] + (double)comp[(k * R + r) * NT];
     }
 }
 
@@ -501,7 +521,8 @@ __device__ __forceinline__ void sym_tile_fp64(const double4* __restrict__ sj, in
                                               const double (&x)[kRowsPerLane], const double (&y)[kRowsPerLane],
                                               const double (&t)[kRowsPerLane], const int (&ct)[kRowsPerLane],
                                               double nab, double nbb, double nae, double nbe,
-                                              double (&a)[6][kRowsPerLane], double* __restrict__ colw, int lane)
+                                              double (&a)[6][kRowsPerLane], double* __restrict__ colw,
+                                              double* __restrict__ red, int lane)
 {
     constexpr int R = kRowsPerLane;
     constexpr int KC = GRAD ? 3 : 1;
@@ -546,7 +567,7 @@ __device__ __forceinline__ void sym_tile_fp64(const double4* __restrict__ sj, in
             }
         }
         double v[3];
-        reduce4_multi<KC>(cp, v);
+        column_sums4<KC>(cp, red, lane, v);
         if ((lane & 15) == 0)
 #pragma unroll
             for (int q = 0; q < KC; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
@@ -562,6 +583,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     constexpr int TB = kRowsPerBlock / kTile;
     __shared__ double4 sj[kTile];
     __shared__ double colred[4][KC][kTile];
+    __shared__ double red_lds[4][4 * 64];
 
     const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
     const PairReq& rq = batch.r[q];
@@ -571,6 +593,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int n = rq.n;
     long long u = (long long)blk * rq.upb;
     const long long uend = min(u + (long long)rq.upb, rq.units);
+    const long long ubeg = u;
+    int prio = -1;
     int I = sym_row_block(u);
     int tile = (int)(u - sym_unit0(I));
 
@@ -581,6 +605,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     bool active = false;
 
     for (; u < uend; ++u) {
+        if (rq.balance) progress_priority(u - ubeg, uend - ubeg, prio);
         if (I != cur) {
             if (cur >= 0) {
 #pragma unroll
@@ -622,11 +647,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0;
         } else if (mode == kFullLow) {
-            sym_tile_fp64<kFullLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, lane);
+            sym_tile_fp64<kFullLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, red_lds[wave], lane);
         } else if (mode == kMaskLow) {
-            sym_tile_fp64<kMaskLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, lane);
+            sym_tile_fp64<kMaskLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, red_lds[wave], lane);
         } else {
-            sym_tile_fp64<kDiag, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, lane);
+            sym_tile_fp64<kDiag, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, red_lds[wave], lane);
         }
         __syncthreads();
         const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;
@@ -797,8 +822,8 @@ hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme,
     const dim3 grid(b.total_items), block(kThreads);
     if (scheme == kSymmetric) {
         if (precision == kFP32C) {
-            if (grad) pair_sym_fp32c<true><<<grid, block, 0, s>>>(b);
-            else pair_sym_fp32c<false><<<grid, block, 0, s>>>(b);
+            if (grad) pair_sym_fp32c<true><<<grid, dim3(kSymThreads), 0, s>>>(b);
+            else pair_sym_fp32c<false><<<grid, dim3(kSymThreads), 0, s>>>(b);
         } else {
             if (grad) pair_sym_fp64<true><<<grid, block, 0, s>>>(b);
             else pair_sym_fp64<false><<<grid, block, 0, s>>>(b);
@@ -818,8 +843,8 @@ int sym_blocks_per_cu(int precision, bool grad)
     int nb = 0;
     hipError_t e;
     if (precision == kFP32C)
-        e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<true>, kThreads, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<false>, kThreads, 0);
+        e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<true>, kSymThreads, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<false>, kSymThreads, 0);
     else
         e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<true>, kThreads, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<false>, kThreads, 0);

@@ -55,7 +55,8 @@ __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0
                                            float t0h, float t0l, const float (&nab)[kMultiTheta],
                                            const float (&nbb)[kMultiTheta], const float (&nae)[kMultiTheta],
                                            const float (&nbe)[kMultiTheta], float (&s)[2 * kMultiTheta][kRowsPerLane],
-                                           float* __restrict__ comp, float* __restrict__ colw, int lane)
+                                           volatile lds_float* comp, float* __restrict__ colw,
+                                           float* __restrict__ red, int lane)
 {
     constexpr int R = kRowsPerLane;
     constexpr int KT = kMultiTheta;
@@ -101,7 +102,7 @@ __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0
                 }
             }
             float v[KT];
-            reduce4_multi<KT>(cp, v);
+            column_sums4<KT>(cp, red, lane, v);
             if ((lane & 15) == 0)
 #pragma unroll
                 for (int q = 0; q < KT; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
@@ -109,7 +110,11 @@ __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0
 #pragma unroll
         for (int k = 0; k < 2 * KT; ++k)
 #pragma unroll
-            for (int r = 0; r < R; ++r) two_sum_into(s[k][r], comp[(k * R + r) * kThreads], p[k][r]);
+            for (int r = 0; r < R; ++r) {
+                float cc = comp[(k * R + r) * kThreads];
+                two_sum_into(s[k][r], cc, p[k][r]);
+                comp[(k * R + r) * kThreads] = cc;
+            }
     }
 }
 
@@ -122,7 +127,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     __shared__ float4 sj[2 * kTile];
     __shared__ float colred[4][KT][kTile];
     __shared__ float comp_lds[K * R * kThreads];
-    float* comp = comp_lds + threadIdx.x;
+    __shared__ float red_lds[4][4 * 64];
+    volatile lds_float* comp = (lds_float*)comp_lds + threadIdx.x;
 
     const int blk = (int)blockIdx.x;
     const int lane = threadIdx.x & 63;
@@ -130,6 +136,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int n = rq.n;
     long long u = (long long)blk * rq.upb;
     const long long uend = min(u + (long long)rq.upb, rq.units);
+    const long long ubeg = u;
+    int prio = -1;
     int I = sym_row_block(u);
     int tile = (int)(u - sym_unit0(I));
 
@@ -149,6 +157,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     bool active = false;
 
     for (; u < uend; ++u) {
+        progress_priority(u - ubeg, uend - ubeg, prio);
         if (I != cur) {
             if (cur >= 0) {
 #pragma unroll
@@ -201,11 +210,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) colw[q * kTile + 4 * lane + k4] = 0.0f;
         } else if (mode == kFullLow) {
-            multi_tile<kFullLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, lane);
+            multi_tile<kFullLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, red_lds[wave], lane);
         } else if (mode == kMaskLow) {
-            multi_tile<kMaskLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, lane);
+            multi_tile<kMaskLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, red_lds[wave], lane);
         } else {
-            multi_tile<kDiag>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, lane);
+            multi_tile<kDiag>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, red_lds[wave], lane);
         }
         __syncthreads();
         const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;

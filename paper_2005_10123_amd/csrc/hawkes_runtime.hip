@@ -242,6 +242,7 @@ hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params&
     memset(&pb, 0, sizeof pb);
     fill_pair(p, d, pl, cv, pb.r[0]);
     pb.r[0].item_begin = 0;
+    pb.r[0].balance = 1;
     pb.nreq = 1;
     pb.total_items = pl.items;
 

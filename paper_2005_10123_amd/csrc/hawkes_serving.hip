@@ -224,6 +224,7 @@ void admit(hawkes_ctx* c, Server* sv)
                 cv.out7 = L.d_out + 8 * nb;
                 fill_pair(p.req.p, *d, pl, cv, pb.r[nb]);
                 pb.r[nb].item_begin = items;
+                pb.r[nb].balance = 0;  // launches overlap here; later batches fill the CUs
                 items += pl.items;
                 fill_epi(p.req.p, *d, pl, grad, p.req.precision, cv, eb.r[nb]);
                 eb.r[nb].item_begin = epi_items;
