@@ -35,17 +35,28 @@ CUS, CLOCK = 256, 2.4e9
 P_OPS32 = 157.3e12 / 2          # FP32 vector: 157.3 TFLOP/s with FMA = 2 FLOP
 P_OPS64 = 78.6e12 / 2           # FP64 vector
 P_EXP32 = CUS * 32 * CLOCK      # v_exp_f32 lanes per second (32 per CU per clock, measured)
-FP64_EXP_OPS = 16               # FP64 lane operations of one exp2 (range reduction + degree-12 poly)
+FP64_EXP_OPS = 16               # FP64 lane operations of one exp2 (range reduction + degree-11 poly)
 
 
-def measured_traffic(kernel_source: str, record: str):
-    """HBM bytes per launch of the pairwise kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
-    recorded in profiles/ (copy-calibrated), or None when the kernel source changed since."""
+KERNEL_SOURCES = ("hawkes_kernels.hip", "hawkes_device.h", "hawkes_internal.h")
+
+
+def kernel_source_sha256() -> str:
+    """sha256 over the sources compiled into the pairwise kernels, in KERNEL_SOURCES order."""
     import hashlib
 
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2005_10123_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(record: str):
+    """HBM bytes per launch of the pairwise kernel from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+    recorded in profiles/ (copy-calibrated), or None when the kernel sources changed since."""
     try:
         rec = json.load(open(record))
-        sha = hashlib.sha256(open(kernel_source, "rb").read()).hexdigest()
+        sha = kernel_source_sha256()
     except OSError:
         return None
     if rec.get("kernel_source_sha256") != sha:
@@ -275,8 +286,7 @@ def main():
                    "n_events": n, "pairs_per_step": pairs},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": roof / 1e9, "unit": "Gpair/s",
                      "frac": achieved / roof,
-                     "traffic": measured_traffic(os.path.join(ROOT, "paper_2005_10123_amd", "csrc", "hawkes_kernels.hip"),
-                                                 os.path.join(ROOT, "profiles", "pair_sym_fp32c_grad_city85k.json")),
+                     "traffic": measured_traffic(os.path.join(ROOT, "profiles", "pair_sym_fp32c_grad_city85k.json")),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
                      "kernel": "pair_sym_fp32c<grad>", "kernel_ms": kms,
                      "model": "1/(13.5 ops / 78.65e12 ops/s + 1.5 exp / 19.66e12 exp/s) per ordered pair (the "

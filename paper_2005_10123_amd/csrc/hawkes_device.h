@@ -146,6 +146,20 @@ __device__ __forceinline__ void progress_priority(long long done, long long tota
     }
 }
 
+// Even split of the work units over the blocks of a launch: block b walks units
+// [split_begin(b), split_begin(b + 1)), the first `rem` blocks one unit more than the others.
+__device__ __forceinline__ long long split_begin(long long b, long long base, long long rem)
+{
+    return b * base + (b < rem ? b : rem);
+}
+
+// The block whose range holds unit u.
+__device__ __forceinline__ long long split_block(long long u, long long base, long long rem)
+{
+    const long long big = rem * (base + 1);
+    return u < big ? u / (base + 1) : rem + (u - big) / base;
+}
+
 // First work unit of each row block: u(I, 0) = TB I (I + 1) / 2, TB tiles per row block.
 __device__ __forceinline__ long long sym_unit0(int I)
 {

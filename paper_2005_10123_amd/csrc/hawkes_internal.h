@@ -51,7 +51,7 @@ struct PairReq {
     int row_blocks;       // npad / kRowsPerBlock
     int splits;           // direct: column ranges the j loop is cut into
     int tiles_per_split;  // direct: kTile-event tiles in each column range
-    int upb;              // symmetric: work units per block
+    int ubase, urem;      // symmetric: block b walks ubase + (b < urem) units (even split)
     int item_begin;       // first work item (block) of this request in the launch
     int balance;          // symmetric: 1 when the launch has the device to itself (progress priority)
     // Negated base-2 exponent coefficients: B = 2^(nab r^2 + nbb dt^2), E = 2^(nae r^2 + nbe dt).
@@ -77,7 +77,7 @@ struct EpiReq {
     double* block_part;   // [nblocks][7]
     double* out7;         // 7 doubles: ell, gradient
     int n, npad, splits, grad;
-    int scheme, row_blocks, upb;
+    int scheme, row_blocks, ubase, urem;
     int nblocks;          // ceil(n / kThreads)
     int item_begin;
     double T;             // largest event time

@@ -406,8 +406,8 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = rq.n;
-    long long u = (long long)blk * rq.upb;
-    const long long uend = min(u + (long long)rq.upb, rq.units);
+    long long u = split_begin(blk, rq.ubase, rq.urem);
+    const long long uend = split_begin(blk + 1, rq.ubase, rq.urem);
     const long long ubeg = u;
     int prio = -1;
     int I = sym_row_block(u);
@@ -591,8 +591,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = rq.n;
-    long long u = (long long)blk * rq.upb;
-    const long long uend = min(u + (long long)rq.upb, rq.units);
+    long long u = split_begin(blk, rq.ubase, rq.urem);
+    const long long uend = split_begin(blk + 1, rq.ubase, rq.urem);
     const long long ubeg = u;
     int prio = -1;
     int I = sym_row_block(u);
@@ -711,8 +711,8 @@ __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
             // Row sums: one partial per block that walked this row block, in block order.
             constexpr long long TB = kRowsPerBlock / kTile;
             const int I = i / kRowsPerBlock, rho = i % kRowsPerBlock;
-            const long long bf = TB * I * (I + 1) / 2 / rq.upb;
-            const long long bl = (TB * (I + 1) * (I + 2) / 2 - 1) / rq.upb;
+            const long long bf = split_block(TB * I * (I + 1) / 2, rq.ubase, rq.urem);
+            const long long bl = split_block(TB * (I + 1) * (I + 2) / 2 - 1, rq.ubase, rq.urem);
             for (long long b = bf; b <= bl; ++b) {
                 const double* ps = rq.part + (size_t)(b + I) * K * kRowsPerBlock + rho;
                 if (rq.grad) {

@@ -25,7 +25,7 @@ struct MultiReq {
     double* part;     // [blocks + row_blocks][2 * kMultiTheta][kRowsPerBlock]
     double* colpart;  // [kMultiTheta][col_stride]
     long long units, col_stride;
-    int n, npad, row_blocks, upb;
+    int n, npad, row_blocks, ubase, urem;
     float nab[kMultiTheta], nbb[kMultiTheta], nae[kMultiTheta], nbe[kMultiTheta];
 };
 
@@ -37,7 +37,7 @@ struct MultiEpi {
     double* block_part;  // [nblocks][kMultiTheta]
     double* out;         // kMultiTheta log-likelihoods
     long long col_stride;
-    int n, npad, row_blocks, upb, nth, nblocks;
+    int n, npad, row_blocks, ubase, urem, nth, nblocks;
     double T;
     double mu0[kMultiTheta], tau_t[kMultiTheta], theta[kMultiTheta], omega[kMultiTheta];
     double cb[kMultiTheta], ce[kMultiTheta];
@@ -134,8 +134,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = rq.n;
-    long long u = (long long)blk * rq.upb;
-    const long long uend = min(u + (long long)rq.upb, rq.units);
+    long long u = split_begin(blk, rq.ubase, rq.urem);
+    const long long uend = split_begin(blk + 1, rq.ubase, rq.urem);
     const long long ubeg = u;
     int prio = -1;
     int I = sym_row_block(u);
@@ -249,8 +249,8 @@ __global__ __launch_bounds__(kThreads) void epilogue_multi(const MultiEpi e)
     double v[KT] = {0, 0, 0, 0};
     if (i < e.n) {
         const int I = i / kRowsPerBlock, rho = i % kRowsPerBlock;
-        const long long bf = TB * I * (I + 1) / 2 / e.upb;
-        const long long bl = (TB * (I + 1) * (I + 2) / 2 - 1) / e.upb;
+        const long long bf = split_block(TB * I * (I + 1) / 2, e.ubase, e.urem);
+        const long long bl = split_block(TB * (I + 1) * (I + 2) / 2 - 1, e.ubase, e.urem);
         double Sb[KT] = {0, 0, 0, 0}, Se[KT] = {0, 0, 0, 0};
         for (long long b = bf; b <= bl; ++b) {
             const double* ps = e.part + (size_t)(b + I) * 2 * KT * kRowsPerBlock + rho;
@@ -331,8 +331,8 @@ static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_p
     const long long T = d.npad / kRowsPerBlock;
     const long long units = TB * T * (T + 1) / 2;
     const long long slots = std::max(1, c->multi_slots);
-    const int upb = (int)std::max<long long>(1, (units + slots - 1) / slots);
-    const int items = (int)((units + upb - 1) / upb);
+    const int items = (int)std::min(slots, units);
+    const int ubase = (int)(units / items), urem = (int)(units % items);
     const long long col_stride = (long long)kRowsPerBlock * T * (T + 1) / 2;
     const int nblocks = (int)((d.n + kThreads - 1) / kThreads);
     const size_t part_d = (size_t)(items + T) * 2 * KT * kRowsPerBlock;
@@ -353,7 +353,8 @@ static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_p
     r.n = (int)d.n;
     r.npad = d.npad;
     r.row_blocks = (int)T;
-    r.upb = upb;
+    r.ubase = ubase;
+    r.urem = urem;
     MultiEpi e;
     memset(&e, 0, sizeof e);
     e.ev64 = d.ev64;
@@ -366,7 +367,8 @@ static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_p
     e.n = (int)d.n;
     e.npad = d.npad;
     e.row_blocks = (int)T;
-    e.upb = upb;
+    e.ubase = ubase;
+    e.urem = urem;
     e.nblocks = nblocks;
     e.T = d.T;
     const double log2e = 1.44269504088896340736, two_pi = 6.28318530717958647693;

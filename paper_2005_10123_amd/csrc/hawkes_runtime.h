@@ -36,7 +36,7 @@ struct Plan {
     int scheme = kSymmetric;
     int row_blocks = 0, splits = 0, tiles_per_split = 0, K = 0, epi_blocks = 0;
     int items = 0;            // blocks of the pairwise kernel
-    int upb = 0;              // symmetric: work units per block
+    int ubase = 0, urem = 0;  // symmetric: block b walks ubase + (b < urem) work units
     long long units = 0;      // symmetric: (row block, column tile) units of the lower triangle
     long long col_stride = 0; // symmetric: doubles per column-sum quantity
     size_t part_doubles = 0;  // row partial sums

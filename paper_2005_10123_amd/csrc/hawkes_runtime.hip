@@ -47,14 +47,16 @@ Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precisio
     pl.K = grad ? 6 : 2;
     pl.epi_blocks = (int)((n + kThreads - 1) / kThreads);
     if (scheme == kSymmetric) {
-        // Equal contiguous ranges of lower-triangle work units, one range per resident block, so
-        // every block of a lone evaluation runs from start to end together with the others.
+        // Contiguous ranges of lower-triangle work units, one range per resident block, their
+        // lengths differing by at most one unit, so every block of a lone evaluation runs from
+        // start to end together with the others and every resident slot is used.
         const long long TB = kRowsPerBlock / kTile;
         const long long T = pl.row_blocks;
         pl.units = TB * T * (T + 1) / 2;
         const long long slots = std::max(1, c->sym_slots[precision == kFP32C ? 1 : 0][grad ? 1 : 0]);
-        pl.upb = (int)std::max<long long>(1, (pl.units + slots - 1) / slots);
-        pl.items = (int)((pl.units + pl.upb - 1) / pl.upb);
+        pl.items = (int)std::min(slots, pl.units);
+        pl.ubase = (int)(pl.units / pl.items);
+        pl.urem = (int)(pl.units % pl.items);
         pl.part_doubles = (size_t)(pl.items + T) * pl.K * kRowsPerBlock;
         pl.col_stride = (long long)kRowsPerBlock * T * (T + 1) / 2;
         pl.col_doubles = (size_t)(grad ? 3 : 1) * pl.col_stride;
@@ -115,7 +117,8 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
     e.grad = grad ? 1 : 0;
     e.scheme = pl.scheme;
     e.row_blocks = pl.row_blocks;
-    e.upb = pl.upb;
+    e.ubase = pl.ubase;
+    e.urem = pl.urem;
     e.nblocks = pl.epi_blocks;
     e.T = d.T;
     e.mu0 = p.mu0;
@@ -145,7 +148,8 @@ void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const C
     r.row_blocks = pl.row_blocks;
     r.splits = pl.splits;
     r.tiles_per_split = pl.tiles_per_split;
-    r.upb = pl.upb;
+    r.ubase = pl.ubase;
+    r.urem = pl.urem;
     fold(p, r);
 }
 
