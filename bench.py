@@ -133,6 +133,30 @@ def cpu_baseline_threads(x, y, t, theta, per_row_s, budget_s=8.0):
                       f"{threads} contiguous row ranges run concurrently; {sec:.1f} s"}
 
 
+THETA_POSTERIOR = (1.0, 1.6, 14.0, 0.153, 1440.0, 0.0695)
+
+
+def posterior_regime(ctx):
+    """FP32C against FP64 (both on the GPU) at the paper's posterior regime, on the 85,000-event
+    15 km / 5,000-day workload: tau_x = 1.6 km and tau_t = 14 days as fixed in Section 2.1, and the
+    Section 3.2 posterior means h = 69.5 m, omega = 1440 per day (1 / omega = one minute),
+    theta = 0.153 (mu0 = 1, not reported).  A stress of binary32 time resolution: reported, not gated."""
+    from paper_2005_10123_amd import synth
+
+    (x, y, t), _ = synth.config_events("city_85k_15km")
+    ds = ctx.dataset(x, y, t)
+    ell32, g32 = ctx.grad(ds, THETA_POSTERIOR, "fp32c")
+    ell64, g64 = ctx.grad(ds, THETA_POSTERIOR, "fp64")
+    rows = ctx.rows(ds, THETA_POSTERIOR, "fp64")
+    ds.close()
+    l1 = np.abs(rows["grad"]).sum(axis=0)
+    floor = abs(ell64) / np.maximum(np.abs(np.asarray(THETA_POSTERIOR)), 1.0)
+    return {"workload": "city_85k_15km", "theta": list(THETA_POSTERIOR), "loglik_fp64": ell64,
+            "ell_rel": abs(ell32 - ell64) / abs(ell64),
+            "grad_l1_normalised": (np.abs(g32 - g64) / np.maximum(l1, floor)).tolist(),
+            "grad_plain_rel": (np.abs(g32 - g64) / np.abs(g64)).tolist()}
+
+
 def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed=4):
     """Closed-loop chains with Poisson think times over 16 resident datasets of log-uniform size."""
     from paper_2005_10123_amd import binding, synth
@@ -304,8 +328,14 @@ def main():
         "loglik": ell,
     }
     ds.close()
+    result["posterior_regime"] = posterior_regime(ctx)
     if not args.no_serving:
         result["serving"] = serving_run(ctx, seconds=args.serving_seconds)
+        result["serving_sweep"] = []
+        for u in (0.5, 1.0, 2.0):
+            r = serving_run(ctx, seconds=3.0, utilisation=u)
+            result["serving_sweep"].append({k: r[k] for k in ("offered_utilisation", "requests", "p50_ms", "p99_ms",
+                                                              "pairs_per_s")})
         result["pi_batch"] = pi_batch_run(ctx)
     ctx.close()
     if not args.no_cpu_baseline:
