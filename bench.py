@@ -157,6 +157,36 @@ def posterior_regime(ctx):
             "grad_plain_rel": (np.abs(g32 - g64) / np.abs(g64)).tolist()}
 
 
+def shard_run(ctx, nshards=8, workload="stress_1m"):
+    """One GPU's share of an evaluation split over `nshards` devices, at its real shape: the
+    pairwise-kernel time of each shard of the 1,000,000-event workload (FP32C, log-likelihood +
+    gradient) next to the whole evaluation's.  The shards run one after another on this GPU; the
+    per-event sums they return (6 doubles per event) are what the devices would add in an
+    all-reduce before hawkes_finish."""
+    from paper_2005_10123_amd import synth
+
+    (x, y, t), theta = synth.config_events(workload)
+    n = x.size
+    ds = ctx.dataset(x, y, t)
+    ctx.grad(ds, theta, "fp32c")
+    ctx.kernel_time(reset=True)
+    ctx.profile(True)
+    ell_whole, _ = ctx.grad(ds, theta, "fp32c")
+    whole_ms, _ = ctx.kernel_time(reset=True)
+    shard_ms, total = [], np.zeros((n, 6))
+    for k in range(nshards):
+        total += ctx.shard_sums(ds, theta, k, nshards, "fp32c")
+        ms, _ = ctx.kernel_time(reset=True)
+        shard_ms.append(ms)
+    ctx.profile(False)
+    ell_sharded, _ = ctx.finish(ds, theta, total)
+    ds.close()
+    return {"workload": workload, "n_events": n, "shards": nshards, "kernel_ms_whole": whole_ms,
+            "kernel_ms_per_shard": shard_ms, "max_shard_share_of_whole": max(shard_ms) / whole_ms,
+            "ell_rel_sharded_vs_whole": abs(ell_sharded - ell_whole) / abs(ell_whole),
+            "exchange_bytes_per_device": n * 6 * 8}
+
+
 def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed=4):
     """Closed-loop chains with Poisson think times over 16 resident datasets of log-uniform size."""
     from paper_2005_10123_amd import binding, synth
@@ -253,11 +283,18 @@ def main():
     ap.add_argument("--workload", default="city_85k_10km")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-shards", action="store_true",
+                    help="skip the one-GPU-share run of the 1,000,000-event workload cut into 8 shards")
+    ap.add_argument("--timing-only", action="store_true",
+                    help="only the timed steps and the FP64 comparison (for profiler runs): implies "
+                         "--no-serving --no-cpu-baseline --no-shards and skips the posterior-regime report")
     ap.add_argument("--serving-seconds", type=float, default=8.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (5 times), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters, then exit")
     args = ap.parse_args()
+    if args.timing_only:
+        args.no_serving = args.no_cpu_baseline = args.no_shards = True
     if args.copy_calibration:
         import torch
 
@@ -328,7 +365,10 @@ def main():
         "loglik": ell,
     }
     ds.close()
-    result["posterior_regime"] = posterior_regime(ctx)
+    if not args.timing_only:
+        result["posterior_regime"] = posterior_regime(ctx)
+    if not args.no_shards:
+        result["shard_share"] = shard_run(ctx)
     if not args.no_serving:
         result["serving"] = serving_run(ctx, seconds=args.serving_seconds)
         result["serving_sweep"] = []

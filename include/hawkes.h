@@ -124,6 +124,29 @@ hawkes_status hawkes_rows(hawkes_ctx* ctx, int32_t id, const hawkes_params* p, i
 hawkes_status hawkes_loglik_multi(hawkes_ctx* ctx, int32_t id, const hawkes_params* thetas, int32_t count,
                                   int precision, double* out_loglik, double* out_pi);
 
+/* ---- one dataset over several devices ----------------------------------------------------------
+ * The log-likelihood equation needs, for every event n, six sums over the other events: the
+ * background sums S_b = sum_n' B(n, n') (n' = n included), S_br = sum r^2 B, S_bt = sum dt^2 B and the
+ * trigger sums S_e = sum_{t_n' < t_n} E(n, n'), S_et = sum dt E, S_er = sum r^2 E, with
+ * B = exp(-r^2 / (2 tau_x^2) - dt^2 / (2 tau_t^2)), E = exp(-omega dt - r^2 / (2 h^2)), r and dt the
+ * distance and time difference of the pair; lambda_n = c_b S_b + c_e S_e (Section 2.1).  The pairs
+ * n' < n (in time order) are cut into `nshards` contiguous ranges of equal work; a device (one
+ * context per device, the dataset registered in each) computes the sums over its range, the
+ * per-event sums of all shards are added (e.g. by an all-reduce), and hawkes_finish turns the totals
+ * into ell and its gradient.  Symmetric enumeration, whatever hawkes_set_pair_scheme chose. */
+
+/* Per-event sums of shard `shard` (0 <= shard < nshards) of the pairwise pass.  out_sums: n * 6
+ * doubles, event k (caller's order) at out_sums[6k .. 6k + 5] = (S_b, S_br, S_bt, S_e, S_et, S_er);
+ * the diagonal term B(n, n) = 1 is in shard 0's S_b.  precision as for hawkes_grad. */
+hawkes_status hawkes_shard_sums(hawkes_ctx* ctx, int32_t id, const hawkes_params* p, int precision, int32_t shard,
+                                int32_t nshards, double* out_sums);
+
+/* ell and, if out_grad is not NULL, its gradient (6 doubles) from the per-event sums `sums` (n * 6
+ * doubles in the layout of hawkes_shard_sums, added over all shards of the same parameters), in
+ * binary64. */
+hawkes_status hawkes_finish(hawkes_ctx* ctx, int32_t id, const hawkes_params* p, const double* sums,
+                            double* out_loglik, double* out_grad);
+
 /* ---- batched serving -------------------------------------------------------------------------
  * Requests from many concurrent samplers (the paper's Algorithm 1 evaluates the likelihood once
  * per Metropolis-Hastings step) are queued, admitted while evaluation slots and the HBM budget

@@ -104,6 +104,8 @@ def load(path: str | None = None):
         "hawkes_set_pair_scheme": ([vp, ctypes.c_int], i32),
         "hawkes_loglik_multi": ([vp, i32, ctypes.POINTER(Params), i32, ctypes.c_int, _dp, _dp], i32),
         "hawkes_kernel_time": ([vp, _dp, ctypes.POINTER(i64), ctypes.c_int], i32),
+        "hawkes_shard_sums": ([vp, i32, ctypes.POINTER(Params), ctypes.c_int, i32, i32, _dp], i32),
+        "hawkes_finish": ([vp, i32, ctypes.POINTER(Params), _dp, _dp, _dp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -197,6 +199,24 @@ class Context:
                                     out.ctypes.data_as(_dp)))
         return {"lambda": out[:, 0].copy(), "Lambda": out[:, 1].copy(), "ell": out[:, 2].copy(),
                 "pi": out[:, 3].copy(), "grad": out[:, 4:10].copy()}
+
+    def shard_sums(self, ds, theta, shard, nshards, precision="fp32c"):
+        """Per-event sums (n, 6) = (S_b, S_br, S_bt, S_e, S_et, S_er) of one shard of the pairwise
+        pass, caller order; the sums of all shards added together go to finish()."""
+        n = ds.n if isinstance(ds, Dataset) else int(self.info(ds)[0])
+        out = np.zeros((n, 6))
+        _check(self.lib.hawkes_shard_sums(self._h, _id(ds), ctypes.byref(params(theta)), _prec(precision),
+                                          int(shard), int(nshards), out.ctypes.data_as(_dp)))
+        return out
+
+    def finish(self, ds, theta, sums):
+        """(ell, gradient) from per-event sums (n, 6) added over all shards."""
+        sums = np.ascontiguousarray(sums, dtype=np.float64)
+        ell = ctypes.c_double()
+        g = np.zeros(6)
+        _check(self.lib.hawkes_finish(self._h, _id(ds), ctypes.byref(params(theta)), sums.ctypes.data_as(_dp),
+                                      ctypes.byref(ell), g.ctypes.data_as(_dp)))
+        return ell.value, g
 
     def loglik_multi(self, ds, thetas, precision="fp32c", want_pi=True):
         """Log-likelihoods (S,) and, with want_pi, self-excitation probabilities (S, n) for S

@@ -16,6 +16,18 @@ constexpr int kChunk = 64;  // pair terms summed plainly in binary32 before a co
 
 enum Mode : int { kNone = 0, kFull = 1, kMask = 2 };
 
+// The request of a batched launch that work item `item` belongs to (items are numbered
+// consecutively over the requests, request k starting at r[k].item_begin).
+template <typename Req>
+__device__ __forceinline__ int find_request(const Req* r, int nreq, int item)
+{
+    int q = 0;
+#pragma unroll 1
+    for (int k = 1; k < nreq; ++k)
+        if (item >= r[k].item_begin) q = k;
+    return q;
+}
+
 // Keep a wave-uniform constant in a vector register: two-operand VALU ops whose operands are all
 // VGPRs issue faster on gfx950 than ones reading a scalar register.
 __device__ __forceinline__ float in_vgpr(float v)
@@ -165,6 +177,14 @@ __device__ __forceinline__ long long sym_unit0(int I)
 {
     constexpr long long TB = kRowsPerBlock / kTile;
     return TB * (long long)I * (I + 1) / 2;
+}
+
+__device__ __forceinline__ int sym_row_block(long long u);
+
+// The first row block J with sym_unit0(J) >= target.
+__device__ __forceinline__ int sym_first_block_from(long long target)
+{
+    return target <= 0 ? 0 : sym_row_block(target - 1) + 1;
 }
 
 __device__ __forceinline__ int sym_row_block(long long u)

@@ -1,0 +1,185 @@
+// hawkes_epilogue.hip -- the per-event epilogue and the final reduction of an evaluation (gfx950).
+//
+//  epilogue -- per event, in binary64: combine the pairwise pass's partial sums in a fixed order
+//     into S_b, S_br, S_bt, S_e, S_et, S_er, then lambda_i = c_b S_b + c_e S_e, Lambda_i (closed
+//     form of Section 2.1), ell_i = log lambda_i - Lambda_i and the six gradient terms; then a
+//     fixed-shape tree reduction per block.
+//  final -- one block per request sums the block partials in a fixed order (the paper's second
+//     kernel, Algorithm 3 step 2, made deterministic).
+#include "hawkes_device.h"
+
+namespace hawkes {
+namespace {
+
+using namespace dev;
+
+__device__ __forceinline__ double std_normal_cdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
+__device__ __forceinline__ double std_normal_pdf(double z) { return exp(-0.5 * z * z) * 0.39894228040143267794; }
+
+// Fixed-shape tree over the block: v[m] of every thread summed into thread 0's v[m].
+__device__ __forceinline__ void block_sum7(double (&v)[7], double (*red)[kThreads])
+{
+#pragma unroll
+    for (int m = 0; m < 7; ++m) red[m][threadIdx.x] = v[m];
+    __syncthreads();
+    for (int stride = kThreads / 2; stride > 0; stride >>= 1) {
+        if ((int)threadIdx.x < stride)
+#pragma unroll
+            for (int m = 0; m < 7; ++m) red[m][threadIdx.x] += red[m][threadIdx.x + stride];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < 7; ++m) v[m] = red[m][0];
+}
+
+__global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
+{
+    __shared__ double red[7][kThreads];
+    const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
+    const EpiReq& rq = batch.r[q];
+    const int blk = (int)blockIdx.x - rq.item_begin;
+    const int i = blk * kThreads + threadIdx.x;
+    const int K = rq.grad ? 6 : 2;
+
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    if (i < rq.n) {
+        double S[6] = {0, 0, 0, 0, 0, 0};  // Sb, Sbr, Sbt, Se, Set, Ser
+        if (rq.sums_in) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) S[k] = rq.sums_in[(size_t)i * 6 + k];
+        } else if (rq.scheme == kSymmetric) {
+            // Row sums: one partial per block that walked a unit of this row block, in block order.
+            constexpr long long TB = kRowsPerBlock / kTile;
+            const int I = i / kRowsPerBlock, rho = i % kRowsPerBlock;
+            const long long lo = max(TB * I * (I + 1) / 2, rq.ubegin);
+            const long long hi = min(TB * (I + 1) * (I + 2) / 2, rq.uend);
+            if (lo < hi) {
+                const long long bf = split_block(lo - rq.ubegin, rq.ubase, rq.urem);
+                const long long bl = split_block(hi - 1 - rq.ubegin, rq.ubase, rq.urem);
+                for (long long b = bf; b <= bl; ++b) {
+                    const double* ps = rq.part + (size_t)(b + I) * K * kRowsPerBlock + rho;
+                    if (rq.grad) {
+#pragma unroll
+                        for (int k = 0; k < 6; ++k) S[k] += ps[(size_t)k * kRowsPerBlock];
+                    } else {
+                        S[0] += ps[0];
+                        S[3] += ps[kRowsPerBlock];
+                    }
+                }
+            }
+            // Column sums: the background terms with every later event, by row block J >= I, from
+            // the units (J, tile of i) that were walked, gathered four row blocks at a time into
+            // four partial sums combined in a fixed order (four independent loads in flight).
+            const long long tile_i = i / kTile;
+            const int J0 = max(I, sym_first_block_from(rq.ubegin - tile_i));
+            const int J1 = min(rq.row_blocks, sym_first_block_from(rq.uend - tile_i));
+            const int KC = rq.grad ? 3 : 1;
+            for (int q = 0; q < KC; ++q) {
+                double acc[4] = {0, 0, 0, 0};
+                const long long off = q * rq.col_stride + i;
+                int J = J0;
+                if (rq.colpart_f32) {
+                    const float* pc = reinterpret_cast<const float*>(rq.colpart) + off;
+                    for (; J + 3 < J1; J += 4)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[u] += pc[(long long)kRowsPerBlock * (J + u) * (J + u + 1) / 2];
+                    for (; J < J1; ++J) acc[0] += pc[(long long)kRowsPerBlock * J * (J + 1) / 2];
+                } else {
+                    const double* pc = rq.colpart + off;
+                    for (; J + 3 < J1; J += 4)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) acc[u] += pc[(long long)kRowsPerBlock * (J + u) * (J + u + 1) / 2];
+                    for (; J < J1; ++J) acc[0] += pc[(long long)kRowsPerBlock * J * (J + 1) / 2];
+                }
+                S[q] += (acc[0] + acc[1]) + (acc[2] + acc[3]);
+            }
+            if (rq.add_diag) S[0] += 1.0;  // the diagonal term B_ii = 1
+        } else {
+            for (int s = 0; s < rq.splits; ++s) {
+                const double* ps = rq.part + (size_t)s * K * rq.npad + i;
+                if (rq.grad) {
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) S[k] += ps[(size_t)k * rq.npad];
+                } else {
+                    S[0] += ps[0];
+                    S[3] += ps[rq.npad];
+                }
+            }
+        }
+        // Moments in dt were summed in scaled time dt' = t_scale dt.
+        S[2] /= rq.t_scale * rq.t_scale;
+        S[4] /= rq.t_scale;
+        if (rq.sums_out) {
+#pragma unroll
+            for (int k = 0; k < 6; ++k) rq.sums_out[(size_t)i * 6 + k] = S[k];
+        } else {
+            const double ti = rq.ev64[i].z;
+            const double mu0 = rq.mu0, tx = rq.tau_x, tt = rq.tau_t, th = rq.theta, om = rq.omega, h = rq.h;
+            const double lam = rq.cb * S[0] + rq.ce * S[3];
+            const double u = rq.T - ti;
+            const double bg_int = std_normal_cdf(u / tt) - std_normal_cdf(-ti / tt);
+            const double Lam = mu0 * bg_int - th * expm1(-om * u);
+            const double ell = log(lam) - Lam;
+            v[0] = ell;
+            double g[6] = {0, 0, 0, 0, 0, 0};
+            if (rq.grad) {
+                const double inv = 1.0 / lam;
+                const double k2pih2 = 1.0 / (6.28318530717958647693 * h * h);
+                g[0] = rq.cb * S[0] / mu0 * inv - bg_int;
+                g[1] = rq.cb * (-2.0 * S[0] / tx + S[1] / (tx * tx * tx)) * inv;
+                g[2] = rq.cb * (-S[0] / tt + S[2] / (tt * tt * tt)) * inv
+                     + (mu0 / (tt * tt)) * (u * std_normal_pdf(u / tt) + ti * std_normal_pdf(ti / tt));
+                g[3] = om * k2pih2 * S[3] * inv + expm1(-om * u);
+                g[4] = th * k2pih2 * (S[3] - om * S[4]) * inv - th * u * exp(-om * u);
+                g[5] = rq.ce * (-2.0 * S[3] / h + S[5] / (h * h * h)) * inv;
+#pragma unroll
+                for (int p = 0; p < 6; ++p) v[1 + p] = g[p];
+            }
+            if (rq.rows_out) {
+                double* o = rq.rows_out + (size_t)i * kRowOut;
+                o[0] = lam;
+                o[1] = Lam;
+                o[2] = ell;
+                o[3] = rq.ce * S[3] / lam;
+#pragma unroll
+                for (int p = 0; p < 6; ++p) o[4 + p] = g[p];
+            }
+        }
+    }
+    block_sum7(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) rq.block_part[(size_t)blk * 7 + m] = v[m];
+}
+
+__global__ __launch_bounds__(kThreads) void final_sum(const EpiBatch batch)
+{
+    __shared__ double red[7][kThreads];
+    const EpiReq& rq = batch.r[blockIdx.x];
+    double v[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int b = threadIdx.x; b < rq.nblocks; b += kThreads)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) v[m] += rq.block_part[(size_t)b * 7 + m];
+    block_sum7(v, red);
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int m = 0; m < 7; ++m) rq.out7[m] = v[m];
+}
+
+}  // namespace
+
+hipError_t launch_epilogue(const EpiBatch& b, hipStream_t s)
+{
+    if (b.total_items <= 0) return hipSuccess;
+    epilogue<<<dim3(b.total_items), dim3(kThreads), 0, s>>>(b);
+    return hipGetLastError();
+}
+
+hipError_t launch_final(const EpiBatch& b, hipStream_t s)
+{
+    if (b.nreq <= 0) return hipSuccess;
+    final_sum<<<dim3(b.nreq), dim3(kThreads), 0, s>>>(b);
+    return hipGetLastError();
+}
+
+}  // namespace hawkes

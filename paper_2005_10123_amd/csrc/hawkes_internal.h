@@ -45,7 +45,9 @@ struct PairReq {
     double* part;         // direct: [splits][K][npad]; symmetric: [blocks + row_blocks][K][kRowsPerBlock]
     double* colpart;      // symmetric: [KC][col_stride] column sums of row block I at RB*I(I+1)/2 + j
                           // (binary32 values in the FP32C pass)
-    long long units;      // symmetric: row_blocks (row_blocks + 1) / 2 * (kRowsPerBlock / kTile)
+    long long units;      // symmetric: work units walked, from ubegin on, of the
+                          // row_blocks (row_blocks + 1) / 2 * (kRowsPerBlock / kTile) of the triangle
+    long long ubegin;     // symmetric: first work unit walked
     long long col_stride; // symmetric: kRowsPerBlock * row_blocks (row_blocks + 1) / 2
     int n, npad;
     int row_blocks;       // npad / kRowsPerBlock
@@ -78,6 +80,10 @@ struct EpiReq {
     double* out7;         // 7 doubles: ell, gradient
     int n, npad, splits, grad;
     int scheme, row_blocks, ubase, urem;
+    long long ubegin, uend;  // symmetric: work units the pairwise pass walked
+    int add_diag;            // add the diagonal background term B_ii = 1
+    double* sums_out;        // if set: write the six per-event sums [n][6] (sorted order) and stop
+    const double* sums_in;   // if set: read the six per-event sums [n][6] instead of partials
     int nblocks;          // ceil(n / kThreads)
     int item_begin;
     double T;             // largest event time

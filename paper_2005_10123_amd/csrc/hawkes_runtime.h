@@ -37,7 +37,8 @@ struct Plan {
     int row_blocks = 0, splits = 0, tiles_per_split = 0, K = 0, epi_blocks = 0;
     int items = 0;            // blocks of the pairwise kernel
     int ubase = 0, urem = 0;  // symmetric: block b walks ubase + (b < urem) work units
-    long long units = 0;      // symmetric: (row block, column tile) units of the lower triangle
+    long long units = 0;      // symmetric: (row block, column tile) units this evaluation walks
+    long long ubegin = 0;     // symmetric: first of them in the row-major order of the lower triangle
     long long col_stride = 0; // symmetric: doubles per column-sum quantity
     size_t part_doubles = 0;  // row partial sums
     size_t col_doubles = 0;   // symmetric: column partial sums
@@ -89,7 +90,10 @@ extern thread_local std::string g_last_error;
 hawkes_status fail(hawkes_status code, const char* fmt, ...);
 hawkes_status hip_fail(hipError_t e, const char* what);
 hawkes_status check_params(const hawkes_params* p);
-Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme);
+// shard / nshards: the evaluation walks the shard-th of nshards contiguous, equal ranges of the
+// symmetric work units (symmetric scheme only; 0 / 1 is the whole triangle).
+Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme, int shard = 0,
+               int nshards = 1);
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows);
 void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const Carved& cv, PairReq& r);
 void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, const Carved& cv,
@@ -101,6 +105,10 @@ Dataset* find_dataset(hawkes_ctx* c, int32_t id);
 void free_dataset(hawkes_ctx* c, Dataset& d);
 
 hawkes_status begin_call(hawkes_ctx* c);
+// Marks the context unusable after a device failure (HAWKES_EDEVICE); returns st.
+hawkes_status poison(hawkes_ctx* c, hawkes_status st);
+// Adds the last profiled pair-kernel time once the stream has passed it.
+void collect_profile(hawkes_ctx* c);
 hawkes_status reserve_blocking(hawkes_ctx* c, size_t need);
 hawkes_status blocking_eval(hawkes_ctx* c, int32_t id, const hawkes_params* p, int precision, bool grad,
                             double out7[7], double* host_rows);

@@ -39,7 +39,7 @@ hawkes_status check_params(const hawkes_params* p)
     return HAWKES_OK;
 }
 
-Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme)
+Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme, int shard, int nshards)
 {
     Plan pl;
     pl.scheme = scheme;
@@ -52,11 +52,13 @@ Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precisio
         // start to end together with the others and every resident slot is used.
         const long long TB = kRowsPerBlock / kTile;
         const long long T = pl.row_blocks;
-        pl.units = TB * T * (T + 1) / 2;
+        const long long all = TB * T * (T + 1) / 2;
+        pl.ubegin = all * shard / nshards;
+        pl.units = all * (shard + 1) / nshards - pl.ubegin;
         const long long slots = std::max(1, c->sym_slots[precision == kFP32C ? 1 : 0][grad ? 1 : 0]);
         pl.items = (int)std::min(slots, pl.units);
-        pl.ubase = (int)(pl.units / pl.items);
-        pl.urem = (int)(pl.units % pl.items);
+        pl.ubase = pl.items > 0 ? (int)(pl.units / pl.items) : 1;
+        pl.urem = pl.items > 0 ? (int)(pl.units % pl.items) : 0;
         pl.part_doubles = (size_t)(pl.items + T) * pl.K * kRowsPerBlock;
         pl.col_stride = (long long)kRowsPerBlock * T * (T + 1) / 2;
         pl.col_doubles = (size_t)(grad ? 3 : 1) * pl.col_stride;
@@ -119,6 +121,9 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
     e.row_blocks = pl.row_blocks;
     e.ubase = pl.ubase;
     e.urem = pl.urem;
+    e.ubegin = pl.ubegin;
+    e.uend = pl.ubegin + pl.units;
+    e.add_diag = 1;
     e.nblocks = pl.epi_blocks;
     e.T = d.T;
     e.mu0 = p.mu0;
@@ -150,6 +155,7 @@ void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const C
     r.tiles_per_split = pl.tiles_per_split;
     r.ubase = pl.ubase;
     r.urem = pl.urem;
+    r.ubegin = pl.ubegin;
     fold(p, r);
 }
 

@@ -43,6 +43,9 @@ def test_null_context_is_rejected_without_device():
     assert lib.hawkes_submit(None, None, 0) == binding.HAWKES_EINVAL
     n = ctypes.c_int32()
     assert lib.hawkes_poll(None, None, 0, ctypes.byref(n), 0) == binding.HAWKES_EINVAL
+    sums = (ctypes.c_double * 6)()
+    assert lib.hawkes_shard_sums(None, 0, ctypes.byref(p), 1, 0, 1, sums) == binding.HAWKES_EINVAL
+    assert lib.hawkes_finish(None, 0, ctypes.byref(p), sums, ctypes.byref(out), None) == binding.HAWKES_EINVAL
     assert lib.hawkes_destroy(None) == binding.HAWKES_OK
     assert lib.hawkes_create(0, 0, None, None) == binding.HAWKES_EINVAL
 
