@@ -365,12 +365,14 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
 constexpr int kSymRows = 4;
 constexpr int kSymThreads = kRowsPerBlock / kSymRows;
 constexpr int kSymWaves = kSymThreads / 64;
+// Waves per SIMD the register budget is sized for (168 VGPRs; three blocks per CU).
+constexpr int kSymWavesPerSimd = 3;
 static_assert(kSymThreads % 64 == 0 && kTile % kSymThreads == 0, "symmetric FP32C block shape");
 
 // The compensation terms of the row sums are touched once per 64 columns, so they live in LDS
 // (one float per thread per accumulator, thread-contiguous) rather than in registers.
 template <bool GRAD>
-__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSymRows == 4 ? 3 : 2))) void pair_sym_fp32c(const PairBatch batch)
+__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSymWavesPerSimd))) void pair_sym_fp32c(const PairBatch batch)
 {
     constexpr int R = kSymRows;
     constexpr int NT = kSymThreads;
@@ -399,7 +401,6 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
     const float tsh = in_vgpr(rq.tsh), tsl = in_vgpr(rq.tsl), nab = in_vgpr(rq.nab);
     const float nae = in_vgpr(rq.nae), kte = in_vgpr(rq.kte);
     float xh[R], yh[R], xl[R], yl[R], ti[R];
-    int ct[R];
     float t0h = 0.0f, t0l = 0.0f;
     float s[6][R];
     int cur = -1, w0 = 0, lrow0 = 0, clo = 0;
@@ -432,7 +433,6 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
                 xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
                 const float tu = (a.z - t0h) + (b.z - t0l);
                 ti[r] = fmaf(tu, tsh, tu * tsl);
-                ct[r] = rq.cut[i];
             }
             clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
 #pragma unroll
@@ -462,11 +462,17 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
         } else if (mode == kFullLow) {
+            int ct[R] = {};  // not read: every column of the tile is causal for every row
             sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
-        } else if (mode == kMaskLow) {
-            sym_tile_fp32<kMaskLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
         } else {
-            sym_tile_fp32<kDiag, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+            // The rows' causal counts are needed only by the few tiles that straddle them.
+            int ct[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) ct[r] = rq.cut[lrow0 + r];
+            if (mode == kMaskLow)
+                sym_tile_fp32<kMaskLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+            else
+                sym_tile_fp32<kDiag, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
         }
         __syncthreads();
         // Column totals of this tile over the block's waves, in wave order (binary32: each is a
