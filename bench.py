@@ -157,6 +157,24 @@ def posterior_regime(ctx):
             "grad_plain_rel": (np.abs(g32 - g64) / np.abs(g64)).tolist()}
 
 
+def loglik_workload(ctx, steps=10):
+    """The log-likelihood-only workload (85,000 events on 15 x 15 km over 5,000 days): both
+    precisions, kernel and call times, FP32C against FP64."""
+    from paper_2005_10123_amd import synth
+
+    (x, y, t), theta = synth.config_events("city_85k_15km")
+    n = x.size
+    ds = ctx.dataset(x, y, t)
+    out = {"workload": "city_85k_15km", "n_events": n, "theta": list(theta)}
+    ell = {}
+    for prec in ("fp32c", "fp64"):
+        ell[prec], wall, _, kms = time_steps(ctx, ds, theta, prec, False, steps, 2)
+        out[prec] = {"ms_per_call": wall / steps * 1e3, "kernel_ms": kms, "pairs_per_s": float(n) * n * steps / wall}
+    ds.close()
+    out["ell_rel_fp32c_vs_fp64"] = abs(ell["fp32c"] - ell["fp64"]) / abs(ell["fp64"])
+    return out
+
+
 def shard_run(ctx, nshards=8, workload="stress_1m"):
     """One GPU's share of an evaluation split over `nshards` devices, at its real shape: the
     pairwise-kernel time of each shard of the 1,000,000-event workload (FP32C, log-likelihood +
@@ -367,6 +385,7 @@ def main():
     ds.close()
     if not args.timing_only:
         result["posterior_regime"] = posterior_regime(ctx)
+        result["loglik_workload"] = loglik_workload(ctx)
     if not args.no_shards:
         result["shard_share"] = shard_run(ctx)
     if not args.no_serving:
