@@ -42,12 +42,17 @@ KERNEL_SOURCES = ("hawkes_kernels.hip", "hawkes_device.h", "hawkes_internal.h")
 
 
 def kernel_source_sha256() -> str:
-    """sha256 over the sources compiled into the pairwise kernels, in KERNEL_SOURCES order."""
+    """sha256 over the code (comments and blank lines dropped) of the sources compiled into the
+    pairwise kernels, in KERNEL_SOURCES order."""
     import hashlib
+    import re
 
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        h.update(open(os.path.join(ROOT, "paper_2005_10123_amd", "csrc", name), "rb").read())
+        text = open(os.path.join(ROOT, "paper_2005_10123_amd", "csrc", name)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", "", text)
+        h.update("\n".join(line.rstrip() for line in text.splitlines() if line.strip()).encode())
     return h.hexdigest()
 
 

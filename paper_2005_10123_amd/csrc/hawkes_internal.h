@@ -33,8 +33,8 @@ enum Precision : int { kFP64 = 0, kFP32C = 1 };
 //   kSymmetric: every unordered pair j < i once (lower triangle).  The background kernel B_ij and
 //               its moments are symmetric, so one evaluation feeds both row i and row j; the
 //               trigger term only ever feeds the later event i.  Work units are (row block I,
-//               column tile t <= diagonal) in row-major order, dealt out in equal contiguous
-//               ranges to a grid sized to the device's resident blocks.
+//               column tile t <= diagonal) in row-major order, dealt out in contiguous ranges
+//               whose lengths differ by at most one to a grid of the device's resident blocks.
 enum Scheme : int { kDirect = 0, kSymmetric = 1 };
 
 // One evaluation's view of its dataset and scratch, passed by value in the kernel arguments.
