@@ -193,6 +193,11 @@ hawkes_status reserve_blocking(hawkes_ctx* c, size_t need)
         server_trim(c);
         st = c->blk.reserve(c, need);
     }
+    if (st == HAWKES_ENOMEM && c->scheme == kSymmetric)
+        // The symmetric enumeration's column partial sums grow as N^2 / 2048 values per quantity
+        // (about 5.9 GB for the FP32C gradient at N = 10^6); the direct one needs O(N).
+        g_last_error += " (the symmetric pair enumeration's scratch grows as N^2; "
+                        "hawkes_set_pair_scheme(ctx, HAWKES_PAIRS_DIRECT) needs memory linear in N)";
     return st;
 }
 

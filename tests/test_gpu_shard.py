@@ -91,3 +91,19 @@ def test_bad_shard_arguments(ctx):
                 ctx.shard_sums(ds, th, k, m, "fp64")
     finally:
         ds.close()
+
+
+def test_shards_ignore_the_context_scheme(ctx):
+    """Shards always walk the symmetric enumeration, whatever the context's pair scheme."""
+    (x, y, t), th = synth.config_events("small_2k", n=2500)
+    ds = ctx.dataset(x, y, t)
+    try:
+        ref = shard_total(ctx, ds, th, 3, "fp64")
+        ctx.set_pair_scheme("direct")
+        try:
+            got = shard_total(ctx, ds, th, 3, "fp64")
+        finally:
+            ctx.set_pair_scheme("symmetric")
+    finally:
+        ds.close()
+    assert np.array_equal(got, ref)
