@@ -74,6 +74,43 @@ __device__ __forceinline__ double exp2_f64(double a)
 
 enum SymMode : int { kSkip = 0, kFullLow = 1, kMaskLow = 2, kDiag = 3 };
 
+// A value that is the same in every lane, moved to scalar registers.
+__device__ __forceinline__ float uniform(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform(double v)
+{
+    const uint2 u = __builtin_bit_cast(uint2, v);
+    return __builtin_bit_cast(double, make_uint2((unsigned)__builtin_amdgcn_readfirstlane((int)u.x),
+                                                 (unsigned)__builtin_amdgcn_readfirstlane((int)u.y)));
+}
+
+// Largest v over the 64 lanes of the wave (every lane receives it).
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
+}
+
+// Time differences in the FP32C passes.  Measuring times from a lane's first row makes a column's
+// time one value shared by the lane's rows (one subtraction per pair), at an absolute error of a
+// few binary32 ulps of the time the lane's rows span.  For a column at least kNearSpans such spans
+// before the rows that is at most 2^-23 / kNearSpans of the difference itself; nearer columns,
+// where the trigger term and the dt-moments of close pairs are decided, take the difference from
+// the hi/lo parts of both events instead (error a binary32 ulp of the difference).
+constexpr float kNearSpans = 8.0f;
+
+// Whether a causal tile staged in LDS (sj: hi, lo float4 pairs of kTile events, time in .z) lies at
+// least kNearSpans lane spans before the wave's first row (t_first: its centred time, hi + lo).
+// Uniform over the wave.
+__device__ __forceinline__ bool far_tile(const float4* __restrict__ sj, float t_first, float span)
+{
+    const float t_last = sj[2 * (kTile - 1)].z + sj[2 * (kTile - 1) + 1].z;
+    return uniform(t_first - t_last) >= kNearSpans * span;
+}
+
 // Lane-rotated copy of v within each 16-lane row (DPP control CTRL, e.g. 0x128 = row_ror:8).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)

@@ -36,11 +36,14 @@ using namespace dev;
 // the background exponent into nab r^2 - dt^2; the epilogue divides the dt-moments by s and s^2.
 // s is applied as s_hi + s_lo: a binary32 s alone would perturb every background exponent by the
 // same relative amount (up to 2^-23), a bias that does not average out over the sum.
-template <int MODE, bool GRAD>
+// EXACT: the time difference of each pair from the hi/lo parts of both events (th, tl: the rows'
+// times), for tiles near the rows; otherwise from the lane's first row (ti, t0h, t0l).
+template <int MODE, bool EXACT, bool GRAD>
 __device__ __forceinline__ void chunk_fp32(const float4* __restrict__ sj, int jbase,
                                            const float (&xh)[kRowsPerLane], const float (&yh)[kRowsPerLane],
                                            const float (&xl)[kRowsPerLane], const float (&yl)[kRowsPerLane],
-                                           const float (&ti)[kRowsPerLane], const int (&ct)[kRowsPerLane],
+                                           const float (&ti)[kRowsPerLane], const float (&th)[kRowsPerLane],
+                                           const float (&tl)[kRowsPerLane], const int (&ct)[kRowsPerLane],
                                            float t0h, float t0l, float tsh, float tsl, float nab, float nae, float kte,
                                            float (&p)[6][kRowsPerLane])
 {
@@ -49,13 +52,22 @@ __device__ __forceinline__ void chunk_fp32(const float4* __restrict__ sj, int jb
     for (int jj = 0; jj < kChunk; ++jj) {
         const float4 hi = sj[2 * jj];
         const float4 lo = sj[2 * jj + 1];
-        const float tu = (hi.z - t0h) + (lo.z - t0l);
-        const float tj = fmaf(tu, tsh, tu * tsl);
+        float tj = 0.0f;
+        if (!EXACT) {
+            const float tu = (hi.z - t0h) + (lo.z - t0l);
+            tj = fmaf(tu, tsh, tu * tsl);
+        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const float dx = (xh[r] - hi.x) + (xl[r] - lo.x);
             const float dy = (yh[r] - hi.y) + (yl[r] - lo.y);
-            const float dt = ti[r] - tj;
+            float dt;
+            if (EXACT) {
+                const float du = (th[r] - hi.z) + (tl[r] - lo.z);
+                dt = fmaf(du, tsh, du * tsl);
+            } else {
+                dt = ti[r] - tj;
+            }
             const float r2 = fmaf(dx, dx, dy * dy);
             const float dt2 = dt * dt;
             const float b = __builtin_amdgcn_exp2f(fmaf(r2, nab, -dt2));
@@ -100,9 +112,9 @@ __global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
 
     const float tsh = in_vgpr(rq.tsh), tsl = in_vgpr(rq.tsl), nab = in_vgpr(rq.nab);
     const float nae = in_vgpr(rq.nae), kte = in_vgpr(rq.kte);
-    float xh[R], yh[R], xl[R], yl[R], ti[R];
+    float xh[R], yh[R], xl[R], yl[R], ti[R], th[R], tl[R];
     int ct[R];
-    float t0h = 0.0f, t0l = 0.0f;
+    float t0h = 0.0f, t0l = 0.0f, lane_span = 0.0f;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = lrow0 + r;
@@ -113,13 +125,19 @@ __global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
             t0l = b.z;
         }
         xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
+        th[r] = a.z; tl[r] = b.z;
         const float tu = (a.z - t0h) + (b.z - t0l);
         ti[r] = fmaf(tu, tsh, tu * tsl);
         ct[r] = rq.cut[i];
+        if (i < n) lane_span = tu;  // rows are time-sorted: the last valid row is the latest
     }
     // Rows are time-sorted, so the causal counts of the wave's rows lie in [clo, chi].
     const int clo = __builtin_amdgcn_readfirstlane(rq.cut[min(wrow0, n - 1)]);
     const int chi = __builtin_amdgcn_readfirstlane(rq.cut[min(wrow0 + 64 * R - 1, n - 1)]);
+    // Causal tiles closer in time to the wave's first row than kNearSpans lane spans, and tiles
+    // straddling the causal counts, take exact time differences (kNearSpans in hawkes_device.h).
+    const float span = uniform(wave_max(lane_span));
+    const float t_first = uniform(rq.ev32[2 * (size_t)min(wrow0, n - 1)].z + rq.ev32[2 * (size_t)min(wrow0, n - 1) + 1].z);
 
     float s[K][R], c[K][R];
 #pragma unroll
@@ -138,7 +156,9 @@ __global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
         sj[2 * threadIdx.x + 1] = src[1];
         __syncthreads();
         if (!active) continue;
-        const int mode = (j0 + kTile <= clo) ? kFull : (j0 >= chi ? kNone : kMask);
+        int mode = (j0 + kTile <= clo) ? kFull : (j0 >= chi ? kNone : kMask);
+        if (mode == kFull && !far_tile(sj, t_first, span))
+            mode = kMask;  // near: the masked path (exact times), whose causal mask passes every pair
         for (int ch = 0; ch < kTile; ch += kChunk) {
             float p[6][R];
 #pragma unroll
@@ -147,11 +167,11 @@ __global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
                 for (int r = 0; r < R; ++r) p[k][r] = 0.0f;
             const float4* tj = sj + 2 * ch;
             if (mode == kNone)
-                chunk_fp32<kNone, GRAD>(tj, j0 + ch, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, p);
+                chunk_fp32<kNone, false, GRAD>(tj, j0 + ch, xh, yh, xl, yl, ti, th, tl, ct, t0h, t0l, tsh, tsl, nab, nae, kte, p);
             else if (mode == kFull)
-                chunk_fp32<kFull, GRAD>(tj, j0 + ch, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, p);
+                chunk_fp32<kFull, false, GRAD>(tj, j0 + ch, xh, yh, xl, yl, ti, th, tl, ct, t0h, t0l, tsh, tsl, nab, nae, kte, p);
             else
-                chunk_fp32<kMask, GRAD>(tj, j0 + ch, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, p);
+                chunk_fp32<kMask, true, GRAD>(tj, j0 + ch, xh, yh, xl, yl, ti, th, tl, ct, t0h, t0l, tsh, tsl, nab, nae, kte, p);
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -287,13 +307,17 @@ template <int MODE, bool GRAD, int R, int NT>
 __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int j0, int lrow0,
                                               const float (&xh)[R], const float (&yh)[R],
                                               const float (&xl)[R], const float (&yl)[R],
-                                              const float (&ti)[R], const int (&ct)[R],
+                                              const float (&ti)[R], const float (&th)[R], const float (&tl)[R],
+                                              const int (&ct)[R],
                                               float t0h, float t0l, float tsh, float tsl, float nab, float nae,
                                               float kte, float (&s)[6][R], volatile lds_float* comp,
                                               float* __restrict__ colw, float* __restrict__ red, int lane)
 {
     constexpr int K = GRAD ? 6 : 2;
     constexpr int KC = GRAD ? 3 : 1;
+    // Tiles far before the rows measure times from the lane's first row; the others take every
+    // time difference from the hi/lo parts of the two events.
+    constexpr bool EXACT = MODE != kFullLow;
     for (int ch = 0; ch < kTile; ch += kChunk) {
         float p[6][R];
 #pragma unroll
@@ -311,14 +335,23 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
             for (int cc = 0; cc < 4; ++cc) {
                 const float4 hi = sj[2 * (g + cc)];
                 const float4 lo = sj[2 * (g + cc) + 1];
-                const float tu = (hi.z - t0h) + (lo.z - t0l);
-                const float tj = fmaf(tu, tsh, tu * tsl);
+                float tj = 0.0f;
+                if (!EXACT) {
+                    const float tu = (hi.z - t0h) + (lo.z - t0l);
+                    tj = fmaf(tu, tsh, tu * tsl);
+                }
                 const int j = j0 + g + cc;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float dx = (xh[r] - hi.x) + (xl[r] - lo.x);
                     const float dy = (yh[r] - hi.y) + (yl[r] - lo.y);
-                    const float dt = ti[r] - tj;
+                    float dt;
+                    if (EXACT) {
+                        const float du = (th[r] - hi.z) + (tl[r] - lo.z);
+                        dt = fmaf(du, tsh, du * tsl);
+                    } else {
+                        dt = ti[r] - tj;
+                    }
                     const float r2 = fmaf(dx, dx, dy * dy);
                     const float dt2 = dt * dt;
                     float ab = fmaf(r2, nab, -dt2);
@@ -365,14 +398,31 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
 constexpr int kSymRows = 4;
 constexpr int kSymThreads = kRowsPerBlock / kSymRows;
 constexpr int kSymWaves = kSymThreads / 64;
-// Waves per SIMD the register budget is sized for (168 VGPRs; three blocks per CU).
-constexpr int kSymWavesPerSimd = 3;
+// Waves per SIMD the register budget is sized for: three with the gradient (168 VGPRs, three
+// blocks per CU); four for the log-likelihood alone (128 VGPRs), which measures faster there.
+template <bool GRAD>
+constexpr int kSymWavesPerSimd = GRAD ? 3 : 4;
 static_assert(kSymThreads % 64 == 0 && kTile % kSymThreads == 0, "symmetric FP32C block shape");
+
+// A lane's row times measured from its first row and scaled by s = tsh + tsl (see the direct
+// pass above), and that origin.
+template <int R>
+__device__ __forceinline__ void lane_times(const float4* __restrict__ ev32, int lrow0, float tsh, float tsl,
+                                           float& t0h, float& t0l, float (&ti)[R])
+{
+    t0h = ev32[2 * (size_t)lrow0].z;
+    t0l = ev32[2 * (size_t)lrow0 + 1].z;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const float tu = (ev32[2 * (size_t)(lrow0 + r)].z - t0h) + (ev32[2 * (size_t)(lrow0 + r) + 1].z - t0l);
+        ti[r] = fmaf(tu, tsh, tu * tsl);
+    }
+}
 
 // The compensation terms of the row sums are touched once per 64 columns, so they live in LDS
 // (one float per thread per accumulator, thread-contiguous) rather than in registers.
 template <bool GRAD>
-__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSymWavesPerSimd))) void pair_sym_fp32c(const PairBatch batch)
+__global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSymWavesPerSimd<GRAD>))) void pair_sym_fp32c(const PairBatch batch)
 {
     constexpr int R = kSymRows;
     constexpr int NT = kSymThreads;
@@ -400,11 +450,14 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
 
     const float tsh = in_vgpr(rq.tsh), tsl = in_vgpr(rq.tsl), nab = in_vgpr(rq.nab);
     const float nae = in_vgpr(rq.nae), kte = in_vgpr(rq.kte);
-    float xh[R], yh[R], xl[R], yl[R], ti[R];
-    float t0h = 0.0f, t0l = 0.0f;
+    float xh[R], yh[R], xl[R], yl[R];
     float s[6][R];
     int cur = -1, w0 = 0, lrow0 = 0, clo = 0;
     bool active = false;
+    float t_first = 0.0f;  // centred time of the wave's first row
+    float span = 0.0f;     // largest time spanned by one lane's rows in the wave
+    float ti[R], t0h = 0.0f, t0l = 0.0f;  // lane-origin row times (kept across tiles without the gradient)
+    float th[R], tl[R];                   // the rows' hi/lo times (likewise)
 
     for (; u < uend; ++u) {
         if (rq.balance) progress_priority(u - ubeg, uend - ubeg, prio);
@@ -421,6 +474,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
             w0 = I * kRowsPerBlock + wave * (64 * R);
             lrow0 = w0 + R * lane;
             active = w0 < n;
+            float lane_span = 0.0f;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int i = lrow0 + r;
@@ -433,7 +487,12 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
                 xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
                 const float tu = (a.z - t0h) + (b.z - t0l);
                 ti[r] = fmaf(tu, tsh, tu * tsl);
+                th[r] = a.z;
+                tl[r] = b.z;
+                if (i < n) lane_span = tu;  // rows are time-sorted: the last valid row is the latest
             }
+            span = uniform(wave_max(lane_span));
+            t_first = uniform(rq.ev32[2 * (size_t)min(w0, n - 1)].z + rq.ev32[2 * (size_t)min(w0, n - 1) + 1].z);
             clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
 #pragma unroll
             for (int k = 0; k < 6; ++k)
@@ -461,18 +520,32 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
             for (int qq = 0; qq < KC; ++qq)
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
-        } else if (mode == kFullLow) {
-            int ct[R] = {};  // not read: every column of the tile is causal for every row
-            sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+        } else if (mode == kFullLow && far_tile(sj, t_first, span)) {
+            // With the gradient the registers are short: the lane-origin row times are formed
+            // per tile instead of being kept live across tiles.
+            if (GRAD) lane_times(rq.ev32, lrow0, tsh, tsl, t0h, t0l, ti);
+            const int ct[R] = {};  // not read: every column of the tile is causal for every row
+            sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, tsh, tsl, nab,
+                                                 nae, kte, s, comp, colw, red_lds[wave], lane);
         } else {
-            // The rows' causal counts are needed only by the few tiles that straddle them.
+            // Tiles that straddle the rows' causal counts or their own positions, and causal tiles
+            // closer in time to the rows than kNearSpans lane spans (taken by the masked path, whose
+            // masks then pass every pair): exact time differences, from the row times loaded here.
             int ct[R];
 #pragma unroll
-            for (int r = 0; r < R; ++r) ct[r] = rq.cut[lrow0 + r];
-            if (mode == kMaskLow)
-                sym_tile_fp32<kMaskLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+            for (int r = 0; r < R; ++r) {
+                ct[r] = rq.cut[lrow0 + r];
+                if (GRAD) {  // short of registers: reloaded here rather than kept
+                    th[r] = rq.ev32[2 * (size_t)(lrow0 + r)].z;
+                    tl[r] = rq.ev32[2 * (size_t)(lrow0 + r) + 1].z;
+                }
+            }
+            if (mode == kDiag)
+                sym_tile_fp32<kDiag, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, tsh, tsl, nab,
+                                                  nae, kte, s, comp, colw, red_lds[wave], lane);
             else
-                sym_tile_fp32<kDiag, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, tsh, tsl, nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+                sym_tile_fp32<kMaskLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, tsh, tsl,
+                                                     nab, nae, kte, s, comp, colw, red_lds[wave], lane);
         }
         __syncthreads();
         // Column totals of this tile over the block's waves, in wave order (binary32: each is a

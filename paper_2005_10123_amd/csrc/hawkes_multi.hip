@@ -51,7 +51,8 @@ template <int MODE>
 __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0, int lrow0,
                                            const float (&xh)[kRowsPerLane], const float (&yh)[kRowsPerLane],
                                            const float (&xl)[kRowsPerLane], const float (&yl)[kRowsPerLane],
-                                           const float (&ti)[kRowsPerLane], const int (&ct)[kRowsPerLane],
+                                           const float (&ti)[kRowsPerLane], const float (&th)[kRowsPerLane],
+                                           const float (&tl)[kRowsPerLane], const int (&ct)[kRowsPerLane],
                                            float t0h, float t0l, const float (&nab)[kMultiTheta],
                                            const float (&nbb)[kMultiTheta], const float (&nae)[kMultiTheta],
                                            const float (&nbe)[kMultiTheta], float (&s)[2 * kMultiTheta][kRowsPerLane],
@@ -60,6 +61,9 @@ __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0
 {
     constexpr int R = kRowsPerLane;
     constexpr int KT = kMultiTheta;
+    // Far tiles measure times from the lane's first row; masked and near ones take each pair's time
+    // difference from the hi/lo parts of both events (see kNearSpans).
+    constexpr bool EXACT = MODE != kFullLow;
     for (int ch = 0; ch < kTile; ch += kChunk) {
         float p[2 * KT][R];
 #pragma unroll
@@ -77,13 +81,13 @@ __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0
             for (int cc = 0; cc < 4; ++cc) {
                 const float4 hi = sj[2 * (g + cc)];
                 const float4 lo = sj[2 * (g + cc) + 1];
-                const float tj = (hi.z - t0h) + (lo.z - t0l);
+                const float tj = EXACT ? 0.0f : (hi.z - t0h) + (lo.z - t0l);
                 const int j = j0 + g + cc;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     const float dx = (xh[r] - hi.x) + (xl[r] - lo.x);
                     const float dy = (yh[r] - hi.y) + (yl[r] - lo.y);
-                    const float dt = ti[r] - tj;
+                    const float dt = EXACT ? (th[r] - hi.z) + (tl[r] - lo.z) : ti[r] - tj;
                     const float r2 = fmaf(dx, dx, dy * dy);
                     const float dt2 = dt * dt;
                     const bool below = MODE != kDiag || j < lrow0 + r;
@@ -149,12 +153,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         nae[q] = in_vgpr(rq.nae[q]);
         nbe[q] = in_vgpr(rq.nbe[q]);
     }
-    float xh[R], yh[R], xl[R], yl[R], ti[R];
-    int ct[R];
-    float t0h = 0.0f, t0l = 0.0f;
+    float xh[R], yh[R], xl[R], yl[R];
     float s[K][R];
     int cur = -1, w0 = 0, lrow0 = 0, clo = 0;
     bool active = false;
+    float t_first = 0.0f;  // centred time of the wave's first row
+    float span = 0.0f;     // largest time spanned by one lane's rows in the wave
 
     for (; u < uend; ++u) {
         progress_priority(u - ubeg, uend - ubeg, prio);
@@ -171,6 +175,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             w0 = I * kRowsPerBlock + wave * (64 * R);
             lrow0 = w0 + R * lane;
             active = w0 < n;
+            float lane_span = 0.0f, t0h = 0.0f, t0l = 0.0f;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int i = lrow0 + r;
@@ -181,9 +186,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                     t0l = b.z;
                 }
                 xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
-                ti[r] = (a.z - t0h) + (b.z - t0l);
-                ct[r] = rq.cut[i];
+                if (i < n) lane_span = (a.z - t0h) + (b.z - t0l);  // time-sorted: the last valid row is the latest
             }
+            span = uniform(wave_max(lane_span));
+            t_first = uniform(rq.ev32[2 * (size_t)min(w0, n - 1)].z + rq.ev32[2 * (size_t)min(w0, n - 1) + 1].z);
             clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
 #pragma unroll
             for (int k = 0; k < K; ++k)
@@ -209,12 +215,33 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             for (int q = 0; q < KT; ++q)
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) colw[q * kTile + 4 * lane + k4] = 0.0f;
-        } else if (mode == kFullLow) {
-            multi_tile<kFullLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, red_lds[wave], lane);
-        } else if (mode == kMaskLow) {
-            multi_tile<kMaskLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, red_lds[wave], lane);
+        } else if (mode == kFullLow && far_tile(sj, t_first, span)) {
+            // Row times from the lane's first row, formed per tile rather than kept live.
+            float ti[R];
+            const float t0h = rq.ev32[2 * (size_t)lrow0].z, t0l = rq.ev32[2 * (size_t)lrow0 + 1].z;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+                ti[r] = (rq.ev32[2 * (size_t)(lrow0 + r)].z - t0h) + (rq.ev32[2 * (size_t)(lrow0 + r) + 1].z - t0l);
+            const int ct[R] = {};  // not read: every column of the tile is causal for every row
+            multi_tile<kFullLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw,
+                                 red_lds[wave], lane);
         } else {
-            multi_tile<kDiag>(sj, j0, lrow0, xh, yh, xl, yl, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw, red_lds[wave], lane);
+            // Straddling tiles and near causal ones (the masked path; its causal mask then passes
+            // every pair): exact time differences from the rows' hi/lo times.
+            int ct[R];
+            float th[R], tl[R];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                ct[r] = rq.cut[lrow0 + r];
+                th[r] = rq.ev32[2 * (size_t)(lrow0 + r)].z;
+                tl[r] = rq.ev32[2 * (size_t)(lrow0 + r) + 1].z;
+            }
+            if (mode == kDiag)
+                multi_tile<kDiag>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, nab, nbb, nae, nbe, s, comp, colw,
+                                  red_lds[wave], lane);
+            else
+                multi_tile<kMaskLow>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, nab, nbb, nae, nbe, s, comp,
+                                     colw, red_lds[wave], lane);
         }
         __syncthreads();
         const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;

@@ -46,3 +46,21 @@ def test_multi_rejects_bad_parameters():
     assert e.value.status == binding.HAWKES_EINVAL
     ds.close()
     ctx.close()
+
+
+def test_multi_posterior_regime_minute_scale():
+    """pi_n over posterior-like samples (1 / omega of about a minute) on data whose offspring follow
+    their parents by minutes over 5,000 days, at 2,000 events (sparse in time)."""
+    x, y, t = synth.simulate(synth.SimSpec(2000, 15.0, 5000.0, 5, 1440.0, 0.0695, 0.153, (78, 2000, 1)))
+    rng = np.random.default_rng(3)
+    base = np.array([1.0, 1.6, 14.0, 0.153, 1440.0, 0.0695])
+    th = base * np.exp(0.05 * rng.standard_normal((4, 6)))
+    ctx = binding.Context(0)
+    ds = ctx.dataset(x, y, t)
+    ll, pi = ctx.loglik_multi(ds, th, "fp32c")
+    for s in range(4):
+        ref = oracle.evaluate(x, y, t, th[s], rows=True)
+        assert abs(ll[s] - ref["ell"]) <= 1e-5 * abs(ref["ell"]), (s, ll[s], ref["ell"])
+        assert np.max(np.abs(pi[s] - ref["row_pi"])) <= 1e-5, s
+    ds.close()
+    ctx.close()

@@ -179,3 +179,31 @@ def test_loglik_workload_sampled(ctx):
     e32 = ctx.loglik(ds, th, "fp32c")
     assert rel(e32, e64) <= TOL["fp32c"]
     ds.close()
+
+
+def test_fp32c_small_bandwidth_over_large_extent(ctx):
+    """Exact coordinate differences: a 50 km extent (centred 10^4 km from the origin) with
+    h = 5 m and tau_x = 50 m, so the terms that matter come from pairs metres apart; the FP32C
+    error may not grow with extent / bandwidth."""
+    rng = np.random.default_rng(11)
+    n = 3000
+    parents = rng.uniform(0, 50, (n // 3, 2)) + 1.0e4
+    kids = np.repeat(parents, 2, axis=0) + rng.normal(0, 0.005, (2 * (n // 3), 2))
+    xy = np.concatenate([parents, kids])
+    t = np.concatenate([rng.uniform(0, 1000, n // 3), np.repeat(rng.uniform(0, 1000, n // 3), 2)])
+    t[n // 3:] += rng.exponential(0.5, 2 * (n // 3))
+    check_full(ctx, xy[:, 0], xy[:, 1], t, (1.0, 0.05, 20.0, 0.5, 2.0, 0.005), "h = 5 m over 50 km")
+
+
+def test_fp32c_minute_scale_triggers_over_long_window(ctx):
+    """Time resolution: 20,000 days of events with offspring minutes after their parents and
+    omega = 1440 per day (1 / omega = one minute), as in the paper's posterior regime."""
+    rng = np.random.default_rng(12)
+    m = 1000
+    tp = rng.uniform(0, 20000, m)
+    xp = rng.uniform(0, 10, (m, 2))
+    tk = tp + rng.exponential(1.0 / 1440.0, m)
+    xk = xp + rng.normal(0, 0.07, (m, 2))
+    t = np.concatenate([tp, tk])
+    xy = np.concatenate([xp, xk])
+    check_full(ctx, xy[:, 0], xy[:, 1], t, (1.0, 1.6, 14.0, 0.153, 1440.0, 0.0695), "minutes over 20,000 days")

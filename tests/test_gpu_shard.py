@@ -62,11 +62,11 @@ def test_shard_sums_match_the_oracle_per_event(ctx, prec):
     if prec == "fp64":
         assert err.max() <= 1e-11, err
     else:
-        # S_b and S_e to the FP32C tolerance; the moments (r^2, dt^2, dt times a term) to 1e-4: a
-        # close pair's dt carries the rounding of the lane's time origin, a few binary32 ulps of
-        # the time spanned by the lane's rows (days at this density).
-        assert err[[0, 3]].max() <= 1e-5, err
-        assert err[[1, 2, 4, 5]].max() <= 1e-4, err
+        # Every sum, the moments (r^2, dt^2, dt times a term) included, to the FP32C tolerance:
+        # pairs close in time take dt from the hi/lo parts of both events, so a close pair's dt
+        # carries one binary32 rounding rather than the rounding of a time origin days away.
+        print("per-event sums, max relative error", err)
+        assert err.max() <= 1e-5, err
 
 
 def test_more_shards_than_work(ctx):
