@@ -210,8 +210,11 @@ def shard_run(ctx, nshards=8, workload="stress_1m"):
             "exchange_bytes_per_device": n * 6 * 8}
 
 
-def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed=4):
-    """Closed-loop chains with Poisson think times over 16 resident datasets of log-uniform size."""
+def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed=4, warmup=1.0,
+                min_requests=10000, max_seconds=20.0):
+    """Closed-loop chains with Poisson think times over 16 resident datasets of log-uniform size.
+    Latencies count from the requests submitted after `warmup` seconds; submission goes on for at
+    least `seconds` and until `min_requests` have been measured (at most `max_seconds`)."""
     from paper_2005_10123_amd import binding, synth
 
     sizes = synth.loguniform_sizes(datasets, 5e3, 1.2e5)
@@ -236,36 +239,40 @@ def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed
     lat, pairs, tag_chain = [], 0.0, {}
     tag = 0
     t_start = time.perf_counter()
-    t_end = t_start + seconds
-    done_all = False
-    while not done_all:
+    t_measure = t_start + warmup
+    issuing = True
+    t_last = t_measure
+    while issuing or tag_chain:
         now = time.perf_counter()
-        due = np.nonzero(waiting & (next_t <= now))[0] if now < t_end else []
+        if issuing and (now - t_start >= max_seconds or (now - t_measure >= seconds and len(lat) >= min_requests)):
+            issuing = False
+        due = np.nonzero(waiting & (next_t <= now))[0] if issuing else []
         if len(due):
             reqs = []
             for k in due:
                 th = theta0 * np.exp(0.1 * rng.standard_normal(6))
                 reqs.append(binding.request(dss[k % datasets], th, "fp32c", True, tag))
-                tag_chain[tag] = k
+                tag_chain[tag] = (k, now >= t_measure)
                 tag += 1
                 waiting[k] = False
             ctx.submit(reqs)
         for r in ctx.poll(cap=512, timeout_us=200):
-            k = tag_chain.pop(r.tag)
+            k, measured = tag_chain.pop(r.tag)
             if r.status != 0:
                 raise RuntimeError(f"request failed with status {r.status}")
-            lat.append((r.t_done_ns - r.t_submit_ns) * 1e-9)
-            pairs += float(sizes[k % datasets]) ** 2
+            if measured:
+                lat.append((r.t_done_ns - r.t_submit_ns) * 1e-9)
+                pairs += float(sizes[k % datasets]) ** 2
+                t_last = time.perf_counter()
             waiting[k] = True
             next_t[k] = time.perf_counter() + rng.exponential(think)
-        done_all = time.perf_counter() >= t_end and not tag_chain
-    wall = time.perf_counter() - t_start
+    wall = t_last - t_measure
     for ds in dss:
         ds.close()
     lat = np.array(lat)
     return {"requests": int(lat.size), "chains": chains, "datasets": datasets, "offered_utilisation": utilisation,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "pairs_per_s": pairs / wall, "seconds": wall,
+            "pairs_per_s": pairs / wall, "seconds": wall, "warmup_seconds": warmup,
             "sizes": [int(s) for s in sizes]}
 
 
@@ -378,7 +385,9 @@ def main():
                               "v_exp_f32 at 32 lanes/CU/clk x 256 CU x 2.4 GHz",
                      "symmetric_model_frac": achieved / (1.0 / (WORK_SYM[0] / P_OPS32 + WORK_SYM[1] / P_EXP32)),
                      "valu_tflops": achieved * 19.0 / 1e12},
+        "p10_ms_step": float(np.percentile(per, 10) * 1e3),
         "p50_ms_step": float(np.percentile(per, 50) * 1e3),
+        "p90_ms_step": float(np.percentile(per, 90) * 1e3),
         "p99_ms_step": float(np.percentile(per, 99) * 1e3),
         "fp64": {"pairs_per_s": pairs * steps64 / wall64, "ms_per_step": wall64 / steps64 * 1e3, "kernel_ms": kms64,
                  "roofline_frac": (pairs / (kms64 * 1e-3)) / roofline_pairs(True, True)},
@@ -397,7 +406,7 @@ def main():
         result["serving"] = serving_run(ctx, seconds=args.serving_seconds)
         result["serving_sweep"] = []
         for u in (0.5, 1.0, 2.0):
-            r = serving_run(ctx, seconds=3.0, utilisation=u)
+            r = serving_run(ctx, seconds=3.0, utilisation=u, min_requests=0)
             result["serving_sweep"].append({k: r[k] for k in ("offered_utilisation", "requests", "p50_ms", "p99_ms",
                                                               "pairs_per_s")})
         result["pi_batch"] = pi_batch_run(ctx)

@@ -297,10 +297,11 @@ __global__ __launch_bounds__(kThreads) void pair_fp64(const PairBatch batch)
 // over the lower triangle.  For each tile a lane forms its rows' pair terms with each column; the
 // background term B and its moments go both to the lane's row sums (registers) and to the
 // column's sums; the trigger term only to the row (the column is the earlier event).  Column sums
-// are reduced over the 64 lanes 4 columns at a time by a transposing tree (below), combined over
-// the block's 4 waves in LDS in a fixed order, and written once per (row block, column).  Row sums
-// are written once per (block, row block) the block touched.  Tiles below a wave's rows need no
-// mask for B; tiles straddling them mask j >= i; tiles above are skipped.
+// are reduced over the 64 lanes 4 columns at a time (column_sums4: through LDS, then DPP row
+// rotations), combined over the block's waves in LDS in a fixed order, and written once per
+// (row block, column).  Row sums are written once per (block, row block) the block touched.
+// Tiles below a wave's rows need no mask for B; tiles straddling them mask j >= i; tiles above
+// are skipped.
 
 // One tile of the FP32C symmetric pass for one wave.
 template <int MODE, bool GRAD, int R, int NT>
