@@ -180,6 +180,41 @@ def loglik_workload(ctx, steps=10):
     return out
 
 
+def zero_skip_run(ctx, steps=10):
+    """Zero-tile skipping (off by default; hawkes_set_zero_tile_skipping): the same evaluations
+    with column tiles whose pair terms are all exactly zero left out.  Reported beside the headline,
+    which always evaluates every pair: the 10 x 10 km / 1,000-day gradient workload, the 15 x 15 km /
+    5,000-day log-likelihood workload, and the paper's posterior parameters on the latter."""
+    from paper_2005_10123_amd import synth
+
+    cases = [("city_85k_10km", None, True), ("city_85k_15km", None, False), ("city_85k_15km", THETA_POSTERIOR, True)]
+    out = []
+    for workload, theta_override, grad in cases:
+        (x, y, t), theta = synth.config_events(workload)
+        if theta_override is not None:
+            theta = theta_override
+        n = x.size
+        ds = ctx.dataset(x, y, t)
+        rec = {"workload": workload, "theta": list(theta), "gradient": grad, "precision": "fp32c"}
+        res = {}
+        for skip in (False, True):
+            ctx.set_zero_tile_skipping(skip)
+            r, wall, _, kms = time_steps(ctx, ds, theta, "fp32c", grad, steps, 2)
+            res[skip] = r
+            rec["skip" if skip else "all_pairs"] = {"ms_per_call": wall / steps * 1e3, "kernel_ms": kms,
+                                                    "pairs_per_s": float(n) * n * steps / wall}
+        ctx.set_zero_tile_skipping(False)
+        ds.close()
+        ell0, ell1 = (res[False][0], res[True][0]) if grad else (res[False], res[True])
+        rec["speedup"] = rec["all_pairs"]["ms_per_call"] / rec["skip"]["ms_per_call"]
+        rec["ell_rel_skip_vs_all_pairs"] = abs(ell1 - ell0) / abs(ell0)
+        if grad:
+            g0, g1 = np.asarray(res[False][1]), np.asarray(res[True][1])
+            rec["grad_rel_skip_vs_all_pairs"] = (np.abs(g1 - g0) / np.maximum(np.abs(g0), 1e-300)).tolist()
+        out.append(rec)
+    return out
+
+
 def shard_run(ctx, nshards=8, workload="stress_1m"):
     """One GPU's share of an evaluation split over `nshards` devices, at its real shape: the
     pairwise-kernel time of each shard of the 1,000,000-event workload (FP32C, log-likelihood +
@@ -400,6 +435,7 @@ def main():
     if not args.timing_only:
         result["posterior_regime"] = posterior_regime(ctx)
         result["loglik_workload"] = loglik_workload(ctx)
+        result["zero_tile_skip"] = zero_skip_run(ctx)
     if not args.no_shards:
         result["shard_share"] = shard_run(ctx)
     if not args.no_serving:

@@ -196,6 +196,21 @@ hawkes_status hawkes_outstanding(hawkes_ctx* ctx, int64_t* n);
 enum { HAWKES_PAIRS_SYMMETRIC = 0, HAWKES_PAIRS_DIRECT = 1 };
 hawkes_status hawkes_set_pair_scheme(hawkes_ctx* ctx, int scheme);
 
+/* Zero-tile skipping (enable = 1; 0, the default, turns it off).  Both kernels of the
+ * log-likelihood equation decay in the time difference: the background term as
+ * exp(-dt^2 / (2 tau_t^2)), the trigger term as exp(-omega dt).  Beyond a separation D(Theta) both
+ * are exactly zero in the arithmetic of the chosen precision (binary32 exponentials below 2^-170
+ * for HAWKES_FP32C, binary64 ones below 2^-1110 for HAWKES_FP64), so the pairs further apart add
+ * nothing to any sum.  With skipping on, the symmetric enumeration leaves out every column tile
+ * whose events all lie at least D before the first event of the row block against which it would
+ * be evaluated; on data spanning many multiples of tau_t and 1/omega most pairs are such.  The
+ * result is the same sum of the same non-zero terms; only its grouping into partial sums changes
+ * (as it does with the device's number of compute units), so it agrees with the unskipped
+ * evaluation to rounding.  Applies to hawkes_loglik, hawkes_grad, hawkes_grad_device, hawkes_rows
+ * and submitted requests made after the call, with the symmetric enumeration; not to
+ * hawkes_loglik_multi or hawkes_shard_sums. */
+hawkes_status hawkes_set_zero_tile_skipping(hawkes_ctx* ctx, int enable);
+
 /* ---- diagnostics -------------------------------------------------------------------------- */
 
 /* Thread-local message describing the calling thread's last failure ("" if none). */

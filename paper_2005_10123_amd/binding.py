@@ -102,6 +102,7 @@ def load(path: str | None = None):
         "hawkes_last_error": ([], ctypes.c_char_p),
         "hawkes_profile": ([vp, ctypes.c_int], i32),
         "hawkes_set_pair_scheme": ([vp, ctypes.c_int], i32),
+        "hawkes_set_zero_tile_skipping": ([vp, ctypes.c_int], i32),
         "hawkes_loglik_multi": ([vp, i32, ctypes.POINTER(Params), i32, ctypes.c_int, _dp, _dp], i32),
         "hawkes_kernel_time": ([vp, _dp, ctypes.POINTER(i64), ctypes.c_int], i32),
         "hawkes_shard_sums": ([vp, i32, ctypes.POINTER(Params), ctypes.c_int, i32, i32, _dp], i32),
@@ -265,6 +266,10 @@ class Context:
     def set_pair_scheme(self, scheme="symmetric"):
         """"symmetric" (default: each unordered pair once) or "direct" (every ordered pair)."""
         _check(self.lib.hawkes_set_pair_scheme(self._h, SCHEMES[scheme] if isinstance(scheme, str) else int(scheme)))
+
+    def set_zero_tile_skipping(self, enable=True):
+        """Leave out the column tiles whose pair terms are all exactly zero (see include/hawkes.h)."""
+        _check(self.lib.hawkes_set_zero_tile_skipping(self._h, 1 if enable else 0))
 
     # -- diagnostics ---------------------------------------------------------------------------
     def profile(self, enable=True):

@@ -233,5 +233,49 @@ __device__ __forceinline__ int sym_row_block(long long u)
     return I;
 }
 
+// Start of the symmetric walk of block blk: it walks units [u, uend), the first being column tile
+// `tile` of row block I; after the last tile of row block I (tile TB (I + 1) - 1) comes row block
+// I + 1 at tile zskip[I + 1] (0 without skipping).  Without zero-tile skipping the units are the
+// lower triangle's (row block, tile) pairs in row-major order, split evenly by the host (ubase,
+// urem); with it they are the same pairs minus each row block's zskip[I] leading tiles, split
+// evenly here.
+struct SymWalk {
+    long long u, uend;
+    int I, tile;
+};
+
+// The row block holding walked unit u under zero-tile skipping: the largest I with zcum[I] <= u.
+__device__ __forceinline__ int zero_row_block(const long long* zcum, int row_blocks, long long u)
+{
+    int lo = 0, hi = row_blocks;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (zcum[mid] <= u)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ SymWalk sym_walk_begin(const PairReq& rq, int blk)
+{
+    SymWalk w;
+    if (rq.zcum) {
+        const long long units = rq.zcum[rq.row_blocks];
+        const long long base = units / rq.items, rem = units % rq.items;
+        w.u = split_begin(blk, base, rem);
+        w.uend = split_begin(blk + 1, base, rem);
+        w.I = zero_row_block(rq.zcum, rq.row_blocks, w.u < units ? w.u : units - 1);
+        w.tile = zero_skip_tiles(rq.zcum, rq.row_blocks)[w.I] + (int)(w.u - rq.zcum[w.I]);
+    } else {
+        w.u = rq.ubegin + split_begin(blk, rq.ubase, rq.urem);
+        w.uend = rq.ubegin + split_begin(blk + 1, rq.ubase, rq.urem);
+        w.I = sym_row_block(w.u);
+        w.tile = (int)(w.u - sym_unit0(w.I));
+    }
+    return w;
+}
+
 }  // namespace dev
 }  // namespace hawkes

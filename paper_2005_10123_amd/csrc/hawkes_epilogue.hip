@@ -51,11 +51,24 @@ __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
             // Row sums: one partial per block that walked a unit of this row block, in block order.
             constexpr long long TB = kRowsPerBlock / kTile;
             const int I = i / kRowsPerBlock, rho = i % kRowsPerBlock;
-            const long long lo = max(TB * I * (I + 1) / 2, rq.ubegin);
-            const long long hi = min(TB * (I + 1) * (I + 2) / 2, rq.uend);
+            long long lo, hi, ubegin, ubase, urem;
+            if (rq.zcum) {  // zero-tile skipping: the walked units and their even split
+                const long long units = rq.zcum[rq.row_blocks];
+                ubegin = 0;
+                ubase = units / rq.pair_items;
+                urem = units % rq.pair_items;
+                lo = rq.zcum[I];
+                hi = rq.zcum[I + 1];
+            } else {
+                ubegin = rq.ubegin;
+                ubase = rq.ubase;
+                urem = rq.urem;
+                lo = max(TB * I * (I + 1) / 2, rq.ubegin);
+                hi = min(TB * (I + 1) * (I + 2) / 2, rq.uend);
+            }
             if (lo < hi) {
-                const long long bf = split_block(lo - rq.ubegin, rq.ubase, rq.urem);
-                const long long bl = split_block(hi - 1 - rq.ubegin, rq.ubase, rq.urem);
+                const long long bf = split_block(lo - ubegin, ubase, urem);
+                const long long bl = split_block(hi - 1 - ubegin, ubase, urem);
                 for (long long b = bf; b <= bl; ++b) {
                     const double* ps = rq.part + (size_t)(b + I) * K * kRowsPerBlock + rho;
                     if (rq.grad) {
@@ -71,8 +84,25 @@ __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
             // the units (J, tile of i) that were walked, gathered four row blocks at a time into
             // four partial sums combined in a fixed order (four independent loads in flight).
             const long long tile_i = i / kTile;
-            const int J0 = max(I, sym_first_block_from(rq.ubegin - tile_i));
-            const int J1 = min(rq.row_blocks, sym_first_block_from(rq.uend - tile_i));
+            int J0, J1;
+            if (rq.zcum) {
+                // Row blocks from the first whose skipped prefix covers this event's tile on
+                // did not walk it (the prefixes grow with the row block).
+                const int* zskip = zero_skip_tiles(rq.zcum, rq.row_blocks);
+                int a = I, b = rq.row_blocks;
+                while (a < b) {
+                    const int mid = (a + b) >> 1;
+                    if (zskip[mid] > tile_i)
+                        b = mid;
+                    else
+                        a = mid + 1;
+                }
+                J0 = I;
+                J1 = a;
+            } else {
+                J0 = max(I, sym_first_block_from(rq.ubegin - tile_i));
+                J1 = min(rq.row_blocks, sym_first_block_from(rq.uend - tile_i));
+            }
             const int KC = rq.grad ? 3 : 1;
             for (int q = 0; q < KC; ++q) {
                 double acc[4] = {0, 0, 0, 0};

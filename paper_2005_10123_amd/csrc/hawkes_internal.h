@@ -55,7 +55,15 @@ struct PairReq {
     int tiles_per_split;  // direct: kTile-event tiles in each column range
     int ubase, urem;      // symmetric: block b walks ubase + (b < urem) units (even split)
     int item_begin;       // first work item (block) of this request in the launch
+    int items;            // work items (blocks) of this request
     int balance;          // symmetric: 1 when the launch has the device to itself (progress priority)
+    // Zero-tile skipping (symmetric scheme; nullptr when off): zcum[I], I <= row_blocks, is the
+    // number of walked units in the row blocks before I, followed by zskip[I] (int), the leading
+    // column tiles of row block I that are not walked: every pair term there is exactly zero
+    // because each of its events is at least zero_dt (time units of the data) after the tile's
+    // last event.  Filled by the zero_prefix kernel.
+    long long* zcum;
+    double zero_dt;
     // Negated base-2 exponent coefficients: B = 2^(nab r^2 + nbb dt^2), E = 2^(nae r^2 + nbe dt).
     // The FP32C pass works in scaled time dt' = ts dt with ts = tsh + tsl = sqrt(-nbb):
     // B = 2^(nab r^2 - dt'^2), E = 2^(nae r^2 + kte dt') with kte = nbe / ts.
@@ -86,6 +94,8 @@ struct EpiReq {
     const double* sums_in;   // if set: read the six per-event sums [n][6] instead of partials
     int nblocks;          // ceil(n / kThreads)
     int item_begin;
+    int pair_items;          // blocks of the pairwise pass (symmetric: the walk's split)
+    const long long* zcum;   // zero-tile skipping: as in PairReq, or nullptr
     double T;             // largest event time
     double mu0, tau_x, tau_t, theta, omega, h;
     double cb, ce;        // background and trigger coefficients
@@ -98,8 +108,20 @@ struct EpiBatch {
     int total_items;
 };
 
+// Kernel arguments are passed by value; keep them within 4 KiB.
+static_assert(sizeof(PairBatch) <= 4096 && sizeof(EpiBatch) <= 4096, "kernel argument block too large");
+
+// The leading column tiles of each row block that zero-tile skipping leaves out (see PairReq).
+__host__ __device__ inline int* zero_skip_tiles(long long* zcum, int row_blocks) { return (int*)(zcum + row_blocks + 1); }
+__host__ __device__ inline const int* zero_skip_tiles(const long long* zcum, int row_blocks)
+{
+    return (const int*)(zcum + row_blocks + 1);
+}
+
 // Kernel launchers (hawkes_kernels.hip).  Each returns the launch's hipError_t.
 hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme, hipStream_t s);
+// Zero-tile skipping tables (zcum, zskip) of the requests that use it; one block per request.
+hipError_t launch_zero_prefix(const PairBatch& b, hipStream_t s);
 // Resident blocks per CU of the symmetric pairwise kernel (for sizing its grid).
 int sym_blocks_per_cu(int precision, bool grad);
 hipError_t launch_epilogue(const EpiBatch& b, hipStream_t s);

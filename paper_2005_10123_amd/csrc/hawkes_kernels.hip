@@ -442,12 +442,13 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = rq.n;
-    long long u = rq.ubegin + split_begin(blk, rq.ubase, rq.urem);
-    const long long uend = rq.ubegin + split_begin(blk + 1, rq.ubase, rq.urem);
+    const SymWalk walk = sym_walk_begin(rq, blk);
+    long long u = walk.u;
+    const long long uend = walk.uend;
     const long long ubeg = u;
     int prio = -1;
-    int I = sym_row_block(u);
-    int tile = (int)(u - sym_unit0(I));
+    int I = walk.I;
+    int tile = walk.tile;
 
     const float tsh = in_vgpr(rq.tsh), tsl = in_vgpr(rq.tsl), nab = in_vgpr(rq.nab);
     const float nae = in_vgpr(rq.nae), kte = in_vgpr(rq.kte);
@@ -564,8 +565,8 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
             }
         }
         if (++tile == TB * (I + 1)) {
-            tile = 0;
             ++I;
+            tile = (rq.zcum && I < rq.row_blocks) ? zero_skip_tiles(rq.zcum, rq.row_blocks)[I] : 0;
         }
     }
     if (cur >= 0) {
@@ -576,6 +577,55 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
                 rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
                     (double)s[k][r] + (double)comp[(k * R + r) * NT];
     }
+}
+
+// Zero-tile skipping tables of one request (one block): for each row block I, zskip[I] = the
+// number of leading column tiles t < TB I whose last event is at least zero_dt before the row
+// block's first event (a prefix: the events are time-sorted), then zcum = the exclusive prefix sum
+// of the walked units TB (I + 1) - zskip[I] in row-block order.  Every pair of a skipped tile is
+// separated by at least zero_dt, for which the host guarantees that both the background and the
+// trigger exponentials are exactly zero in the pass's arithmetic.
+__global__ __launch_bounds__(kThreads) void zero_prefix(const PairBatch batch)
+{
+    constexpr int TB = kRowsPerBlock / kTile;
+    __shared__ long long part[kThreads];
+    const PairReq& rq = batch.r[blockIdx.x];
+    if (!rq.zcum) return;
+    const int RB = rq.row_blocks;
+    int* zskip = zero_skip_tiles(rq.zcum, RB);
+    const int per = (RB + kThreads - 1) / kThreads;
+    const int I0 = min(RB, (int)threadIdx.x * per), I1 = min(RB, I0 + per);
+    long long walked = 0;
+    for (int I = I0; I < I1; ++I) {
+        const double t_first = rq.ev64[(size_t)I * kRowsPerBlock].z;
+        int lo = 0, hi = TB * I;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (t_first - rq.ev64[(size_t)mid * kTile + kTile - 1].z >= rq.zero_dt)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        zskip[I] = lo;
+        walked += TB * (I + 1) - lo;
+    }
+    part[threadIdx.x] = walked;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long acc = 0;
+        for (int k = 0; k < kThreads; ++k) {
+            const long long v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+    }
+    __syncthreads();
+    long long acc = part[threadIdx.x];
+    for (int I = I0; I < I1; ++I) {
+        rq.zcum[I] = acc;
+        acc += TB * (I + 1) - zskip[I];
+    }
+    if (I0 < I1 && I1 == RB) rq.zcum[RB] = acc;
 }
 
 // FP64 symmetric pass: same walk, binary64 pair terms and plain binary64 sums.
@@ -654,12 +704,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = rq.n;
-    long long u = rq.ubegin + split_begin(blk, rq.ubase, rq.urem);
-    const long long uend = rq.ubegin + split_begin(blk + 1, rq.ubase, rq.urem);
+    const SymWalk walk = sym_walk_begin(rq, blk);
+    long long u = walk.u;
+    const long long uend = walk.uend;
     const long long ubeg = u;
     int prio = -1;
-    int I = sym_row_block(u);
-    int tile = (int)(u - sym_unit0(I));
+    int I = walk.I;
+    int tile = walk.tile;
 
     double x[R], y[R], t[R];
     int ct[R];
@@ -723,8 +774,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             rq.colpart[qq * rq.col_stride + cb] = colred[0][qq][threadIdx.x] + colred[1][qq][threadIdx.x] +
                                                   colred[2][qq][threadIdx.x] + colred[3][qq][threadIdx.x];
         if (++tile == TB * (I + 1)) {
-            tile = 0;
             ++I;
+            tile = (rq.zcum && I < rq.row_blocks) ? zero_skip_tiles(rq.zcum, rq.row_blocks)[I] : 0;
         }
     }
     if (cur >= 0) {
@@ -739,6 +790,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 }
 
 }  // namespace
+
+hipError_t launch_zero_prefix(const PairBatch& b, hipStream_t s)
+{
+    if (b.nreq <= 0) return hipSuccess;
+    zero_prefix<<<dim3(b.nreq), dim3(kThreads), 0, s>>>(b);
+    return hipGetLastError();
+}
 
 hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme, hipStream_t s)
 {

@@ -30,10 +30,12 @@ struct Dataset {
     int inflight = 0;       // submitted requests not yet completed
 };
 
-// How one evaluation is cut into blocks; a function of (n, grad) only, so a request's arithmetic
-// is identical whether it runs alone, blocking, or batched with others.
+// How one evaluation is cut into blocks; a function of the dataset's size, the kind of evaluation
+// and the context's settings only, so a request's arithmetic is identical whether it runs alone,
+// blocking, or batched with others.
 struct Plan {
     int scheme = kSymmetric;
+    int precision = kFP64;
     int row_blocks = 0, splits = 0, tiles_per_split = 0, K = 0, epi_blocks = 0;
     int items = 0;            // blocks of the pairwise kernel
     int ubase = 0, urem = 0;  // symmetric: block b walks ubase + (b < urem) work units
@@ -42,11 +44,14 @@ struct Plan {
     long long col_stride = 0; // symmetric: doubles per column-sum quantity
     size_t part_doubles = 0;  // row partial sums
     size_t col_doubles = 0;   // symmetric: column partial sums
+    bool zskip = false;       // symmetric: zero-tile skipping (tables zcum, zskip in the scratch)
+    size_t zbytes = 0;        // bytes of those tables
 };
 
 // One evaluation's scratch carved out of a buffer.
 struct Carved {
     double *part = nullptr, *colpart = nullptr, *block_part = nullptr, *out7 = nullptr, *rows = nullptr;
+    long long* zcum = nullptr;  // zero-tile skipping tables, when the plan uses them
 };
 
 struct Scratch {
@@ -80,6 +85,7 @@ struct hawkes_ctx {
     int64_t pair_launches = 0;
     hawkes::Server* server = nullptr;
     int scheme = hawkes::kSymmetric;  // how pair terms are enumerated (hawkes_set_pair_scheme)
+    bool zero_skip = false;           // zero-tile skipping (hawkes_set_zero_tile_skipping)
     int sym_slots[2][2] = {{0, 0}, {0, 0}};  // [precision][grad] resident blocks of the symmetric kernel
     int multi_slots = 0;                     // resident blocks of the multi-parameter kernel
 };
@@ -91,9 +97,10 @@ hawkes_status fail(hawkes_status code, const char* fmt, ...);
 hawkes_status hip_fail(hipError_t e, const char* what);
 hawkes_status check_params(const hawkes_params* p);
 // shard / nshards: the evaluation walks the shard-th of nshards contiguous, equal ranges of the
-// symmetric work units (symmetric scheme only; 0 / 1 is the whole triangle).
+// symmetric work units (symmetric scheme only; 0 / 1 is the whole triangle).  zero_skip: leave out
+// the column tiles whose pair terms are all exactly zero (symmetric scheme, whole triangle only).
 Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme, int shard = 0,
-               int nshards = 1);
+               int nshards = 1, bool zero_skip = false);
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows);
 void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const Carved& cv, PairReq& r);
 void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, const Carved& cv,

@@ -39,10 +39,12 @@ hawkes_status check_params(const hawkes_params* p)
     return HAWKES_OK;
 }
 
-Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme, int shard, int nshards)
+Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme, int shard, int nshards,
+               bool zero_skip)
 {
     Plan pl;
     pl.scheme = scheme;
+    pl.precision = precision;
     pl.row_blocks = npad / kRowsPerBlock;
     pl.K = grad ? 6 : 2;
     pl.epi_blocks = (int)((n + kThreads - 1) / kThreads);
@@ -62,6 +64,12 @@ Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precisio
         pl.part_doubles = (size_t)(pl.items + T) * pl.K * kRowsPerBlock;
         pl.col_stride = (long long)kRowsPerBlock * T * (T + 1) / 2;
         pl.col_doubles = (size_t)(grad ? 3 : 1) * pl.col_stride;
+        if (zero_skip && shard == 0 && nshards == 1) {
+            // Leaving tiles out only shortens the walk: the grid and the partial-sum slots stay
+            // those of the whole triangle.
+            pl.zskip = true;
+            pl.zbytes = ((size_t)(T + 1) * sizeof(long long) + (size_t)T * sizeof(int) + 7) & ~(size_t)7;
+        }
         return pl;
     }
     const int tiles = npad / kTile;
@@ -80,7 +88,7 @@ Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precisio
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows)
 {
     size_t b = (pl.part_doubles + pl.col_doubles) * sizeof(double) + (size_t)pl.epi_blocks * 7 * sizeof(double) +
-               8 * sizeof(double);
+               8 * sizeof(double) + pl.zbytes;
     if (rows) b += (size_t)n * kRowOut * sizeof(double);
     return b;
 }
@@ -125,6 +133,8 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
     e.uend = pl.ubegin + pl.units;
     e.add_diag = 1;
     e.nblocks = pl.epi_blocks;
+    e.pair_items = pl.items;
+    e.zcum = cv.zcum;
     e.T = d.T;
     e.mu0 = p.mu0;
     e.tau_x = p.tau_x;
@@ -137,6 +147,19 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
     PairReq folded;
     fold(p, folded);
     e.t_scale = precision == kFP32C ? (double)folded.tsh + (double)folded.tsl : 1.0;
+}
+
+// Time separation from which both exponentials of a pair are exactly zero in the pass's
+// arithmetic: the base-2 exponents nbb dt^2 (background) and nbe dt (trigger) are then at most
+// -170, far below binary32's smallest subnormal 2^-149 (FP32C), or at most -1110, where the
+// binary64 exponential is clamped to 2^-1100 = 0 (FP64).  The spatial parts only lower them.
+double zero_separation(const hawkes_params& p, int precision)
+{
+    const double log2e = 1.44269504088896340736;
+    const double c = precision == kFP32C ? 170.0 : 1110.0;
+    const double background = p.tau_t * std::sqrt(2.0 * c / log2e);
+    const double trigger = c / (p.omega * log2e);
+    return std::max(background, trigger);
 }
 
 void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const Carved& cv, PairReq& r)
@@ -156,6 +179,9 @@ void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const C
     r.ubase = pl.ubase;
     r.urem = pl.urem;
     r.ubegin = pl.ubegin;
+    r.items = pl.items;
+    r.zcum = cv.zcum;
+    r.zero_dt = zero_separation(p, pl.precision);
     fold(p, r);
 }
 
@@ -228,7 +254,7 @@ void Scratch::release(hawkes_ctx* c)
 }
 
 // Carve one evaluation's scratch: row partials, column partials, block partials, 7 result doubles,
-// per-row output.
+// zero-tile skipping tables, per-row output.
 Carved carve(char* base, const Plan& pl, int64_t n, bool rows)
 {
     Carved cv;
@@ -241,6 +267,8 @@ Carved carve(char* base, const Plan& pl, int64_t n, bool rows)
     p += (size_t)pl.epi_blocks * 7;
     cv.out7 = p;
     p += 8;
+    cv.zcum = pl.zskip ? (long long*)p : nullptr;
+    p += pl.zbytes / sizeof(double);
     cv.rows = rows ? p : nullptr;
     return cv;
 }
@@ -249,7 +277,7 @@ hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params&
                            char* scratch, double* out7_override, double** out7_used, double** rows_out,
                            bool want_rows, hipStream_t s)
 {
-    const Plan pl = make_plan(c, d.n, d.npad, grad, precision, c->scheme);
+    const Plan pl = make_plan(c, d.n, d.npad, grad, precision, c->scheme, 0, 1, c->zero_skip);
     Carved cv = carve(scratch, pl, d.n, want_rows);
     if (out7_override) cv.out7 = out7_override;
 
@@ -272,6 +300,10 @@ hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params&
     if (c->profile) {
         e = hipEventRecord(c->prof_ev[0], s);
         if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    }
+    if (pl.zskip) {
+        e = launch_zero_prefix(pb, s);
+        if (e != hipSuccess) return hip_fail(e, "zero-tile table launch");
     }
     e = launch_pair(pb, precision, grad, pl.scheme, s);
     if (e != hipSuccess) return hip_fail(e, "pair kernel launch");
@@ -336,7 +368,7 @@ hawkes_status blocking_eval(hawkes_ctx* c, int32_t id, const hawkes_params* p, i
     Dataset* d = find_dataset(c, id);
     if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
     const bool want_rows = host_rows != nullptr;
-    const Plan pl = make_plan(c, d->n, d->npad, grad, precision, c->scheme);
+    const Plan pl = make_plan(c, d->n, d->npad, grad, precision, c->scheme, 0, 1, c->zero_skip);
     if ((st = reserve_blocking(c, scratch_bytes(pl, d->n, want_rows))) != HAWKES_OK) return st;
     hipStream_t s = c->stream;
     hipError_t e = hipStreamWaitEvent(s, c->blk_free, 0);
@@ -611,7 +643,7 @@ hawkes_status hawkes_grad_device(hawkes_ctx* c, int32_t id, const hawkes_params*
     std::lock_guard<std::mutex> lk(c->mu);
     Dataset* d = find_dataset(c, id);
     if (!d) return fail(HAWKES_ENOTFOUND, "no dataset %d", id);
-    const Plan pl = make_plan(c, d->n, d->npad, true, precision, c->scheme);
+    const Plan pl = make_plan(c, d->n, d->npad, true, precision, c->scheme, 0, 1, c->zero_skip);
     if ((st = reserve_blocking(c, scratch_bytes(pl, d->n, false))) != HAWKES_OK) return st;
     hipStream_t s = (hipStream_t)hip_stream;  // NULL: the null stream
     // The scratch is shared with every other blocking or device call of this context.
@@ -632,6 +664,15 @@ hawkes_status hawkes_set_pair_scheme(hawkes_ctx* c, int scheme)
         return fail(HAWKES_EINVAL, "unknown pair scheme %d", scheme);
     std::lock_guard<std::mutex> lk(c->mu);
     c->scheme = scheme == HAWKES_PAIRS_DIRECT ? kDirect : kSymmetric;
+    return HAWKES_OK;
+}
+
+hawkes_status hawkes_set_zero_tile_skipping(hawkes_ctx* c, int enable)
+{
+    if (!c) return fail(HAWKES_EINVAL, "ctx is NULL");
+    if (enable != 0 && enable != 1) return fail(HAWKES_EINVAL, "enable must be 0 or 1, not %d", enable);
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->zero_skip = enable != 0;
     return HAWKES_OK;
 }
 

@@ -196,9 +196,11 @@ void admit(hawkes_ctx* c, Server* sv)
         std::vector<Pending> back;  // could not get memory now: return to the queue front
         std::vector<hawkes_result> failed;
         int scheme = kSymmetric;
+        bool zero_skip = false;
         {
             std::lock_guard<std::mutex> lk(c->mu);
             scheme = c->scheme;
+            zero_skip = c->zero_skip;
             for (size_t k = 0; k < cand.size(); ++k) {
                 const Pending& p = cand[k];
                 Dataset* d = find_dataset(c, p.req.dataset);
@@ -207,7 +209,7 @@ void admit(hawkes_ctx* c, Server* sv)
                     continue;
                 }
                 const bool grad = p.req.want_grad != 0;
-                const Plan pl = make_plan(c, d->n, d->npad, grad, p.req.precision, scheme);
+                const Plan pl = make_plan(c, d->n, d->npad, grad, p.req.precision, scheme, 0, 1, zero_skip);
                 const size_t need = scratch_bytes(pl, d->n, false);
                 int bi = back.empty() ? get_buffer(c, sv, need) : -1;
                 if (bi < 0) {
@@ -247,7 +249,9 @@ void admit(hawkes_ctx* c, Server* sv)
         sv->next_stream = (sv->next_stream + 1) % kStreams;
         const int prec = L.req[0].req.precision;
         const bool grad = L.req[0].req.want_grad != 0;
-        hipError_t e = launch_pair(pb, prec, grad, scheme, s);
+        hipError_t e = hipSuccess;
+        if (zero_skip && scheme == kSymmetric) e = launch_zero_prefix(pb, s);
+        if (e == hipSuccess) e = launch_pair(pb, prec, grad, scheme, s);
         if (e == hipSuccess) e = launch_epilogue(eb, s);
         if (e == hipSuccess) e = launch_final(eb, s);
         if (e == hipSuccess) e = hipMemcpyAsync(L.h_out, L.d_out, (size_t)nb * 8 * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -46,6 +46,7 @@ def test_null_context_is_rejected_without_device():
     sums = (ctypes.c_double * 6)()
     assert lib.hawkes_shard_sums(None, 0, ctypes.byref(p), 1, 0, 1, sums) == binding.HAWKES_EINVAL
     assert lib.hawkes_finish(None, 0, ctypes.byref(p), sums, ctypes.byref(out), None) == binding.HAWKES_EINVAL
+    assert lib.hawkes_set_zero_tile_skipping(None, 1) == binding.HAWKES_EINVAL
     assert lib.hawkes_destroy(None) == binding.HAWKES_OK
     assert lib.hawkes_create(0, 0, None, None) == binding.HAWKES_EINVAL
 
