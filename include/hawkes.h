@@ -206,9 +206,10 @@ hawkes_status hawkes_set_pair_scheme(hawkes_ctx* ctx, int scheme);
  * be evaluated; on data spanning many multiples of tau_t and 1/omega most pairs are such.  The
  * result is the same sum of the same non-zero terms; only its grouping into partial sums changes
  * (as it does with the device's number of compute units), so it agrees with the unskipped
- * evaluation to rounding.  Applies to hawkes_loglik, hawkes_grad, hawkes_grad_device, hawkes_rows
- * and submitted requests made after the call, with the symmetric enumeration; not to
- * hawkes_loglik_multi or hawkes_shard_sums. */
+ * evaluation to rounding.  Applies to hawkes_loglik, hawkes_grad, hawkes_grad_device, hawkes_rows,
+ * hawkes_loglik_multi (a tile is left out when the terms of every parameter vector of its pass
+ * vanish there) and submitted requests made after the call, with the symmetric enumeration; not
+ * to hawkes_shard_sums. */
 hawkes_status hawkes_set_zero_tile_skipping(hawkes_ctx* ctx, int enable);
 
 /* ---- diagnostics -------------------------------------------------------------------------- */

@@ -258,7 +258,8 @@ __device__ __forceinline__ int zero_row_block(const long long* zcum, int row_blo
     return lo;
 }
 
-__device__ __forceinline__ SymWalk sym_walk_begin(const PairReq& rq, int blk)
+template <typename Req>
+__device__ __forceinline__ SymWalk sym_walk_begin(const Req& rq, int blk)
 {
     SymWalk w;
     if (rq.zcum) {

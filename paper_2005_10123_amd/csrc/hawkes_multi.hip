@@ -24,8 +24,9 @@ struct MultiReq {
     const int* cut;
     double* part;     // [blocks + row_blocks][2 * kMultiTheta][kRowsPerBlock]
     double* colpart;  // [kMultiTheta][col_stride]
-    long long units, col_stride;
-    int n, npad, row_blocks, ubase, urem;
+    long long* zcum;  // zero-tile skipping tables (as in PairReq) for all vectors of the pass, or nullptr
+    long long units, col_stride, ubegin;
+    int n, npad, row_blocks, ubase, urem, items;
     float nab[kMultiTheta], nbb[kMultiTheta], nae[kMultiTheta], nbe[kMultiTheta];
 };
 
@@ -33,6 +34,8 @@ struct MultiEpi {
     const double4* ev64;
     const double* part;
     const double* colpart;
+    const long long* zcum;  // as in MultiReq
+    int items;              // blocks of the pairwise pass
     double* pi_out;      // [nth][n] in sorted order, or nullptr
     double* block_part;  // [nblocks][kMultiTheta]
     double* out;         // kMultiTheta log-likelihoods
@@ -138,12 +141,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = rq.n;
-    long long u = split_begin(blk, rq.ubase, rq.urem);
-    const long long uend = split_begin(blk + 1, rq.ubase, rq.urem);
+    const SymWalk walk = sym_walk_begin(rq, blk);
+    long long u = walk.u;
+    const long long uend = walk.uend;
     const long long ubeg = u;
     int prio = -1;
-    int I = sym_row_block(u);
-    int tile = (int)(u - sym_unit0(I));
+    int I = walk.I;
+    int tile = walk.tile;
 
     float nab[KT], nbb[KT], nae[KT], nbe[KT];
 #pragma unroll
@@ -250,8 +254,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
             rq.colpart[q * rq.col_stride + cb] = (double)colred[0][q][threadIdx.x] + (double)colred[1][q][threadIdx.x] +
                                                  (double)colred[2][q][threadIdx.x] + (double)colred[3][q][threadIdx.x];
         if (++tile == TB * (I + 1)) {
-            tile = 0;
             ++I;
+            tile = (rq.zcum && I < rq.row_blocks) ? zero_skip_tiles(rq.zcum, rq.row_blocks)[I] : 0;
         }
     }
     if (cur >= 0) {
@@ -276,8 +280,27 @@ __global__ __launch_bounds__(kThreads) void epilogue_multi(const MultiEpi e)
     double v[KT] = {0, 0, 0, 0};
     if (i < e.n) {
         const int I = i / kRowsPerBlock, rho = i % kRowsPerBlock;
-        const long long bf = split_block(TB * I * (I + 1) / 2, e.ubase, e.urem);
-        const long long bl = split_block(TB * (I + 1) * (I + 2) / 2 - 1, e.ubase, e.urem);
+        long long bf, bl;
+        int J1 = e.row_blocks;
+        if (e.zcum) {  // zero-tile skipping: the walked units, split evenly; see the single-Theta epilogue
+            const long long units = e.zcum[e.row_blocks];
+            const long long base = units / e.items, rem = units % e.items;
+            bf = split_block(e.zcum[I], base, rem);
+            bl = split_block(e.zcum[I + 1] - 1, base, rem);
+            const int* zskip = zero_skip_tiles(e.zcum, e.row_blocks);
+            const int tile_i = i / kTile;
+            int a = I;
+            while (a < J1) {
+                const int mid = (a + J1) >> 1;
+                if (zskip[mid] > tile_i)
+                    J1 = mid;
+                else
+                    a = mid + 1;
+            }
+        } else {
+            bf = split_block(TB * I * (I + 1) / 2, e.ubase, e.urem);
+            bl = split_block(TB * (I + 1) * (I + 2) / 2 - 1, e.ubase, e.urem);
+        }
         double Sb[KT] = {0, 0, 0, 0}, Se[KT] = {0, 0, 0, 0};
         for (long long b = bf; b <= bl; ++b) {
             const double* ps = e.part + (size_t)(b + I) * 2 * KT * kRowsPerBlock + rho;
@@ -287,7 +310,7 @@ __global__ __launch_bounds__(kThreads) void epilogue_multi(const MultiEpi e)
                 Se[q] += ps[(size_t)(2 * q + 1) * kRowsPerBlock];
             }
         }
-        for (int J = I; J < e.row_blocks; ++J) {
+        for (int J = I; J < J1; ++J) {
             const double* pc = e.colpart + (long long)kRowsPerBlock * J * (J + 1) / 2 + i;
 #pragma unroll
             for (int q = 0; q < KT; ++q) Sb[q] += pc[q * e.col_stride];
@@ -365,7 +388,9 @@ static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_p
     const size_t part_d = (size_t)(items + T) * 2 * KT * kRowsPerBlock;
     const size_t col_d = (size_t)KT * col_stride;
     const size_t pi_d = out_pi ? (size_t)KT * d.n : 0;
-    const size_t need = (part_d + col_d + (size_t)nblocks * KT + 8 + pi_d) * sizeof(double);
+    const bool zero_skip = c->zero_skip;
+    const size_t z_d = zero_skip ? ((size_t)(T + 1) * sizeof(long long) + (size_t)T * sizeof(int) + 7) / 8 : 0;
+    const size_t need = (part_d + col_d + (size_t)nblocks * KT + 8 + pi_d + z_d) * sizeof(double);
     hawkes_status st = reserve_blocking(c, need);
     if (st != HAWKES_OK) return st;
     double* base = (double*)c->blk.base;
@@ -382,6 +407,7 @@ static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_p
     r.row_blocks = (int)T;
     r.ubase = ubase;
     r.urem = urem;
+    r.items = items;
     MultiEpi e;
     memset(&e, 0, sizeof e);
     e.ev64 = d.ev64;
@@ -390,6 +416,16 @@ static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_p
     e.block_part = base + part_d + col_d;
     e.out = e.block_part + (size_t)nblocks * KT;
     e.pi_out = out_pi ? e.out + 8 : nullptr;
+    r.zcum = zero_skip ? (long long*)(e.out + 8 + pi_d) : nullptr;
+    e.zcum = r.zcum;
+    e.items = items;
+    // Zero-tile tables of each pass: the tiles where the pair terms of all its vectors vanish.
+    PairBatch zb;
+    memset(&zb, 0, sizeof zb);
+    zb.nreq = 1;
+    zb.r[0].ev64 = d.ev64;
+    zb.r[0].row_blocks = (int)T;
+    zb.r[0].zcum = r.zcum;
     e.col_stride = col_stride;
     e.n = (int)d.n;
     e.npad = d.npad;
@@ -418,6 +454,13 @@ static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_p
             e.omega[q] = p.omega;
             e.cb[q] = p.mu0 / (std::pow(two_pi, 1.5) * p.tau_x * p.tau_x * p.tau_t);
             e.ce[q] = p.theta * p.omega / (two_pi * p.h * p.h);
+        }
+        if (zero_skip) {
+            double zdt = 0.0;
+            for (int q = 0; q < nth; ++q) zdt = std::max(zdt, zero_separation(th[s0 + q], kFP32C));
+            zb.r[0].zero_dt = zdt;
+            err = launch_zero_prefix(zb, s);
+            if (err != hipSuccess) break;
         }
         pair_multi_fp32c<<<dim3(items), dim3(kThreads), 0, s>>>(r);
         epilogue_multi<<<dim3(nblocks), dim3(kThreads), 0, s>>>(e);

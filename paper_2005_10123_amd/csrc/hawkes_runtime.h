@@ -102,6 +102,9 @@ hawkes_status check_params(const hawkes_params* p);
 Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme, int shard = 0,
                int nshards = 1, bool zero_skip = false);
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows);
+// Time separation from which a pair's background and trigger exponentials are both exactly zero
+// in the arithmetic of `precision` (zero-tile skipping).
+double zero_separation(const hawkes_params& p, int precision);
 void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const Carved& cv, PairReq& r);
 void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, const Carved& cv,
               EpiReq& e);

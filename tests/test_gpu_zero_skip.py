@@ -121,3 +121,24 @@ def test_skipping_is_faster_on_long_windows(ctx):
         ds.close()
     print("pairwise pass ms without / with skipping:", times[False], times[True])
     assert times[True] <= 0.5 * times[False], times
+
+
+def test_multi_with_skipping_matches_unskipped(ctx):
+    """pi_n and ell for several parameter vectors per pass: a tile is left out only where the
+    terms of every vector of the pass vanish."""
+    x, y, t = long_window(6000, 5000.0, 5)
+    rng = np.random.default_rng(6)
+    th = np.array(THETA) * np.exp(0.1 * rng.standard_normal((6, 6)))
+    ds = ctx.dataset(x, y, t)
+    try:
+        ll0, pi0 = ctx.loglik_multi(ds, th, "fp32c")
+        ctx.set_zero_tile_skipping(True)
+        ll1, pi1 = ctx.loglik_multi(ds, th, "fp32c")
+    finally:
+        ctx.set_zero_tile_skipping(False)
+        ds.close()
+    assert np.max(np.abs(ll1 - ll0) / np.abs(ll0)) <= 1e-10, (ll1, ll0)
+    assert np.max(np.abs(pi1 - pi0)) <= 1e-9
+    ref = oracle.evaluate(x, y, t, th[0], rows=True)
+    assert rel(ll1[0], ref["ell"]) <= TOL["fp32c"]
+    assert np.max(np.abs(pi1[0] - ref["row_pi"])) <= TOL["fp32c"]
