@@ -1,6 +1,7 @@
 """Batched serving through hawkes_submit / hawkes_poll: each result equals the blocking evaluation
 alone (bitwise: same plan, same arithmetic) whatever it is batched with; invalid requests fail
-alone; a small HBM budget queues work instead of failing; destroying a busy dataset is refused."""
+alone; a small HBM budget queues work instead of failing; destroying a busy dataset is refused;
+destroying the context with requests in flight is clean; several threads may submit at once."""
 import numpy as np
 import pytest
 
@@ -115,4 +116,55 @@ def test_dataset_busy_while_requests_in_flight():
     assert e.value.status == binding.HAWKES_EBUSY
     drain(ctx, 8)
     ds.close()
+    ctx.close()
+
+
+def test_destroy_with_requests_in_flight():
+    """Destroying a context while its requests are queued or running waits for the device, drops
+    them and frees everything; the device is usable afterwards."""
+    import time
+
+    ctx = binding.Context(0)
+    (ds,) = datasets(ctx, [20000], seed0=44)
+    theta0 = np.array(synth.THETA_CFG1)
+    ctx.submit([binding.request(ds, theta0 * (1.0 + 0.01 * k), "fp32c", True, k) for k in range(40)])
+    a = time.time()
+    ctx.close()
+    assert time.time() - a < 30.0
+    ctx2 = binding.Context(0)
+    (ds2,) = datasets(ctx2, [700], seed0=45)
+    ell, g = ctx2.grad(ds2, theta0, "fp64")
+    assert np.isfinite(ell) and np.all(np.isfinite(g))
+    ds2.close()
+    ctx2.close()
+
+
+def test_submit_from_many_threads():
+    """One context shared by several submitting threads (as chains would): every request completes
+    once, with the blocking result."""
+    import threading
+
+    ctx = binding.Context(0)
+    dss = datasets(ctx, [2000, 5000], seed0=46)
+    theta0 = np.array(synth.THETA_CFG1)
+    rng = np.random.default_rng(9)
+    thetas = theta0 * np.exp(0.1 * rng.standard_normal((64, 6)))
+    want = [ctx.grad(dss[k % 2], thetas[k], "fp32c") for k in range(64)]
+
+    def worker(w):
+        for k in range(w, 64, 4):
+            ctx.submit([binding.request(dss[k % 2], thetas[k], "fp32c", True, k)])
+
+    threads = [threading.Thread(target=worker, args=(w,)) for w in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    got = drain(ctx, 64)
+    assert sorted(got) == list(range(64))
+    for k in range(64):
+        assert got[k].status == 0
+        assert got[k].loglik == want[k][0] and np.array_equal(np.array(got[k].grad[:]), want[k][1]), k
+    for d in dss:
+        d.close()
     ctx.close()
