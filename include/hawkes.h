@@ -214,7 +214,9 @@ hawkes_status hawkes_set_zero_tile_skipping(hawkes_ctx* ctx, int enable);
 
 /* ---- diagnostics -------------------------------------------------------------------------- */
 
-/* Thread-local message describing the calling thread's last failure ("" if none). */
+/* Thread-local message describing the calling thread's last failure ("" if none).  With the
+ * environment variable HAWKES_LOG set (to anything but "0") each such message is also printed to
+ * stderr when it is recorded. */
 const char* hawkes_last_error(void);
 
 /* Turn on (1) or off (0) device-event timing of the pairwise kernel on the launching stream, and

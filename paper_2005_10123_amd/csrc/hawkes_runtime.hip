@@ -7,12 +7,23 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <numeric>
 
 namespace hawkes {
 
 thread_local std::string g_last_error;
+
+// HAWKES_LOG set to a non-empty value other than "0" also prints every failure to stderr.
+static bool log_failures()
+{
+    static const bool on = [] {
+        const char* v = std::getenv("HAWKES_LOG");
+        return v && *v && std::strcmp(v, "0") != 0;
+    }();
+    return on;
+}
 
 hawkes_status fail(hawkes_status code, const char* fmt, ...)
 {
@@ -22,6 +33,7 @@ hawkes_status fail(hawkes_status code, const char* fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_last_error = buf;
+    if (log_failures()) std::fprintf(stderr, "libhawkes: status %d: %s\n", (int)code, buf);
     return code;
 }
 

@@ -54,3 +54,19 @@ def test_null_context_is_rejected_without_device():
 def test_missing_library_fails_loudly(tmp_path):
     with pytest.raises(ImportError):
         binding.load(str(tmp_path / "nope.so"))
+
+
+def test_failures_are_logged_when_asked(tmp_path):
+    """HAWKES_LOG=1 prints each recorded failure message to stderr (read once per process)."""
+    import sys
+
+    code = ("import ctypes; from paper_2005_10123_amd import binding; lib = binding.load(); "
+            "out = ctypes.c_double(); p = binding.params([1, 0.5, 20, 0.3, 0.5, 0.1]); "
+            "lib.hawkes_loglik(None, 0, ctypes.byref(p), 1, ctypes.byref(out))")
+    env = dict(os.environ, HAWKES_LOG="1", PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert r.returncode == 0, r.stderr
+    assert "libhawkes: status -1: ctx is NULL" in r.stderr
+    env["HAWKES_LOG"] = "0"
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert "libhawkes" not in r.stderr
