@@ -32,6 +32,36 @@ __device__ __forceinline__ void block_sum7(double (&v)[7], double (*red)[kThread
     for (int m = 0; m < 7; ++m) v[m] = red[m][0];
 }
 
+// Adds to S[0..KC) one event's column partial sums (pc: its entry in row block 0's layout,
+// quantities `stride` apart) over row blocks [J0, J1): per quantity four running sums taking row
+// blocks in turn, combined in a fixed order; every quantity's loads of a step are issued together.
+template <int KC, typename T>
+__device__ __forceinline__ void column_totals(const T* __restrict__ pc, long long stride, int J0, int J1, double (&S)[6])
+{
+    double acc[KC][4];
+#pragma unroll
+    for (int q = 0; q < KC; ++q)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[q][u] = 0.0;
+    int J = J0;
+    for (; J + 3 < J1; J += 4) {
+        T v[4][KC];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < KC; ++q) v[u][q] = pc[q * stride + (long long)kRowsPerBlock * (J + u) * (J + u + 1) / 2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int q = 0; q < KC; ++q) acc[q][u] += (double)v[u][q];
+    }
+    for (; J < J1; ++J)
+#pragma unroll
+        for (int q = 0; q < KC; ++q) acc[q][0] += (double)pc[q * stride + (long long)kRowsPerBlock * J * (J + 1) / 2];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) S[q] += (acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]);
+}
+
 __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
 {
     __shared__ double red[7][kThreads];
@@ -103,25 +133,18 @@ __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
                 J0 = max(I, sym_first_block_from(rq.ubegin - tile_i));
                 J1 = min(rq.row_blocks, sym_first_block_from(rq.uend - tile_i));
             }
-            const int KC = rq.grad ? 3 : 1;
-            for (int q = 0; q < KC; ++q) {
-                double acc[4] = {0, 0, 0, 0};
-                const long long off = q * rq.col_stride + i;
-                int J = J0;
-                if (rq.colpart_f32) {
-                    const float* pc = reinterpret_cast<const float*>(rq.colpart) + off;
-                    for (; J + 3 < J1; J += 4)
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) acc[u] += pc[(long long)kRowsPerBlock * (J + u) * (J + u + 1) / 2];
-                    for (; J < J1; ++J) acc[0] += pc[(long long)kRowsPerBlock * J * (J + 1) / 2];
-                } else {
-                    const double* pc = rq.colpart + off;
-                    for (; J + 3 < J1; J += 4)
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) acc[u] += pc[(long long)kRowsPerBlock * (J + u) * (J + u + 1) / 2];
-                    for (; J < J1; ++J) acc[0] += pc[(long long)kRowsPerBlock * J * (J + 1) / 2];
-                }
-                S[q] += (acc[0] + acc[1]) + (acc[2] + acc[3]);
+            if (rq.colpart_f32) {
+                const float* pc = reinterpret_cast<const float*>(rq.colpart) + i;
+                if (rq.grad)
+                    column_totals<3>(pc, rq.col_stride, J0, J1, S);
+                else
+                    column_totals<1>(pc, rq.col_stride, J0, J1, S);
+            } else {
+                const double* pc = rq.colpart + i;
+                if (rq.grad)
+                    column_totals<3>(pc, rq.col_stride, J0, J1, S);
+                else
+                    column_totals<1>(pc, rq.col_stride, J0, J1, S);
             }
             if (rq.add_diag) S[0] += 1.0;  // the diagonal term B_ii = 1
         } else {
