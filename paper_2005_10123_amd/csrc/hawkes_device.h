@@ -72,7 +72,9 @@ __device__ __forceinline__ double exp2_f64(double a)
     return ldexp(p, (int)k);
 }
 
-enum SymMode : int { kSkip = 0, kFullLow = 1, kMaskLow = 2, kDiag = 3 };
+// Symmetric-pass tile modes.  kFullLowB / kFullLowE: an unmasked far tile where every trigger /
+// every background term is exactly zero (zero-tile skipping), so only the other kernel is formed.
+enum SymMode : int { kSkip = 0, kFullLow = 1, kMaskLow = 2, kDiag = 3, kFullLowB = 4, kFullLowE = 5 };
 
 // A value that is the same in every lane, moved to scalar registers.
 __device__ __forceinline__ float uniform(float v)
@@ -233,16 +235,35 @@ __device__ __forceinline__ int sym_row_block(long long u)
     return I;
 }
 
-// Start of the symmetric walk of block blk: it walks units [u, uend), the first being column tile
-// `tile` of row block I; after the last tile of row block I (tile TB (I + 1) - 1) comes row block
-// I + 1 at tile zskip[I + 1] (0 without skipping).  Without zero-tile skipping the units are the
-// lower triangle's (row block, tile) pairs in row-major order, split evenly by the host (ubase,
-// urem); with it they are the same pairs minus each row block's zskip[I] leading tiles, split
-// evenly here.
+// Start of the symmetric walk of block blk: it walks units [u, uend) in order, the first being the
+// k-th walked tile of row block I (walk_tile); after the last of row block I comes row block I + 1
+// at k = 0.  Without zero-tile skipping the units are the lower triangle's (row block, tile) pairs
+// in row-major order, split evenly by the host (ubase, urem); with it they are the same pairs minus
+// each row block's zskip[I] leading tiles, split evenly here.
 struct SymWalk {
     long long u, uend;
-    int I, tile;
+    int I, k;  // the current unit: the k-th walked tile of row block I
 };
+
+// Tile of the k-th walked unit of row block I.  Without skipping: tile k.  With zero-tile
+// skipping the row block's walked tiles [zskip[I], TB (I + 1)) are visited outside-in (first,
+// last, second, second-to-last, ...): the far tiles at one end, which skipping leaves cheap (one
+// kernel only), and the near, masked ones at the other, which cost most, alternate, so the short
+// contiguous unit ranges of the blocks carry similar work.
+__device__ __forceinline__ int walk_tile(const long long* zcum, int row_blocks, int I, int k)
+{
+    constexpr int TB = kRowsPerBlock / kTile;
+    const int first = zero_skip_tiles(zcum, row_blocks)[I];
+    const int n = TB * (I + 1) - first;
+    return first + ((k & 1) ? n - 1 - (k >> 1) : (k >> 1));
+}
+
+// Walked units of row block I.
+__device__ __forceinline__ int walk_units(const long long* zcum, int row_blocks, int I)
+{
+    constexpr int TB = kRowsPerBlock / kTile;
+    return TB * (I + 1) - (zcum ? zero_skip_tiles(zcum, row_blocks)[I] : 0);
+}
 
 // The row block holding walked unit u under zero-tile skipping: the largest I with zcum[I] <= u.
 __device__ __forceinline__ int zero_row_block(const long long* zcum, int row_blocks, long long u)
@@ -268,12 +289,12 @@ __device__ __forceinline__ SymWalk sym_walk_begin(const Req& rq, int blk)
         w.u = split_begin(blk, base, rem);
         w.uend = split_begin(blk + 1, base, rem);
         w.I = zero_row_block(rq.zcum, rq.row_blocks, w.u < units ? w.u : units - 1);
-        w.tile = zero_skip_tiles(rq.zcum, rq.row_blocks)[w.I] + (int)(w.u - rq.zcum[w.I]);
+        w.k = (int)(w.u - rq.zcum[w.I]);
     } else {
         w.u = rq.ubegin + split_begin(blk, rq.ubase, rq.urem);
         w.uend = rq.ubegin + split_begin(blk + 1, rq.ubase, rq.urem);
         w.I = sym_row_block(w.u);
-        w.tile = (int)(w.u - sym_unit0(w.I));
+        w.k = (int)(w.u - sym_unit0(w.I));
     }
     return w;
 }

@@ -64,6 +64,9 @@ struct PairReq {
     // last event.  Filled by the zero_prefix kernel.
     long long* zcum;
     double zero_dt;
+    // With zcum set, the FP32C pass also drops one kernel on far tiles at least zero_gap_b (every
+    // background term zero) or zero_gap_e (every trigger term zero) time units before the rows.
+    float zero_gap_b, zero_gap_e;
     // Negated base-2 exponent coefficients: B = 2^(nab r^2 + nbb dt^2), E = 2^(nae r^2 + nbe dt).
     // The FP32C pass works in scaled time dt' = ts dt with ts = tsh + tsl = sqrt(-nbb):
     // B = 2^(nab r^2 - dt'^2), E = 2^(nae r^2 + kte dt') with kte = nbe / ts.
@@ -119,7 +122,9 @@ __host__ __device__ inline const int* zero_skip_tiles(const long long* zcum, int
 }
 
 // Kernel launchers (hawkes_kernels.hip).  Each returns the launch's hipError_t.
-hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme, hipStream_t s);
+// zskip: the requests use zero-tile skipping (PairReq::zcum set), served by its own variant of the
+// symmetric kernels.
+hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme, bool zskip, hipStream_t s);
 // Zero-tile skipping tables (zcum, zskip) of the requests that use it; one block per request.
 hipError_t launch_zero_prefix(const PairBatch& b, hipStream_t s);
 // Resident blocks per CU of the symmetric pairwise kernel (for sizing its grid).

@@ -318,7 +318,15 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
     constexpr int KC = GRAD ? 3 : 1;
     // Tiles far before the rows measure times from the lane's first row; the others take every
     // time difference from the hi/lo parts of the two events.
-    constexpr bool EXACT = MODE != kFullLow;
+    constexpr bool FAR = MODE == kFullLow || MODE == kFullLowB || MODE == kFullLowE;
+    constexpr bool EXACT = !FAR;
+    constexpr bool DO_B = MODE != kFullLowE;  // background terms (and the column sums)
+    constexpr bool DO_E = MODE != kFullLowB;  // trigger terms
+    if (!DO_B)
+#pragma unroll
+        for (int qq = 0; qq < KC; ++qq)
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
     for (int ch = 0; ch < kTile; ch += kChunk) {
         float p[6][R];
 #pragma unroll
@@ -354,43 +362,53 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
                         dt = ti[r] - tj;
                     }
                     const float r2 = fmaf(dx, dx, dy * dy);
-                    const float dt2 = dt * dt;
-                    float ab = fmaf(r2, nab, -dt2);
-                    if (MODE == kDiag) ab = (j < lrow0 + r) ? ab : -INFINITY;
-                    const float b = __builtin_amdgcn_exp2f(ab);
-                    p[0][r] += b;
-                    cp[0][cc] += b;
-                    if (GRAD) {
-                        p[1][r] = fmaf(r2, b, p[1][r]);
-                        p[2][r] = fmaf(dt2, b, p[2][r]);
-                        cp[1][cc] = fmaf(r2, b, cp[1][cc]);
-                        cp[2][cc] = fmaf(dt2, b, cp[2][cc]);
+                    if (DO_B) {
+                        const float dt2 = dt * dt;
+                        float ab = fmaf(r2, nab, -dt2);
+                        if (MODE == kDiag) ab = (j < lrow0 + r) ? ab : -INFINITY;
+                        const float b = __builtin_amdgcn_exp2f(ab);
+                        p[0][r] += b;
+                        cp[0][cc] += b;
+                        if (GRAD) {
+                            p[1][r] = fmaf(r2, b, p[1][r]);
+                            p[2][r] = fmaf(dt2, b, p[2][r]);
+                            cp[1][cc] = fmaf(r2, b, cp[1][cc]);
+                            cp[2][cc] = fmaf(dt2, b, cp[2][cc]);
+                        }
                     }
-                    float ae = fmaf(r2, nae, dt * kte);
-                    if (MODE != kFullLow) ae = (j < ct[r]) ? ae : -INFINITY;
-                    const float e = __builtin_amdgcn_exp2f(ae);
-                    const int ke = GRAD ? 3 : 1;
-                    p[ke][r] += e;
-                    if (GRAD) {
-                        p[4][r] = fmaf(dt, e, p[4][r]);
-                        p[5][r] = fmaf(r2, e, p[5][r]);
+                    if (DO_E) {
+                        float ae = fmaf(r2, nae, dt * kte);
+                        if (!FAR) ae = (j < ct[r]) ? ae : -INFINITY;
+                        const float e = __builtin_amdgcn_exp2f(ae);
+                        const int ke = GRAD ? 3 : 1;
+                        p[ke][r] += e;
+                        if (GRAD) {
+                            p[4][r] = fmaf(dt, e, p[4][r]);
+                            p[5][r] = fmaf(r2, e, p[5][r]);
+                        }
                     }
                 }
             }
-            float v[3];
-            column_sums4<KC>(cp, red, lane, v);
-            if ((lane & 15) == 0)
+            if (DO_B) {
+                float v[3];
+                column_sums4<KC>(cp, red, lane, v);
+                if ((lane & 15) == 0)
 #pragma unroll
-                for (int q = 0; q < KC; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
+                    for (int q = 0; q < KC; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
+            }
         }
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int k = 0; k < K; ++k) {
+            // Quantities 0 .. K/2 - 1 are background sums, the rest trigger sums; the kernel a mode
+            // leaves out adds exact zeros, which the compensated sums would not change.
+            if ((k < K / 2 && !DO_B) || (k >= K / 2 && !DO_E)) continue;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 float cc = comp[(k * R + r) * NT];
                 two_sum_into(s[k][r], cc, p[k][r]);
                 comp[(k * R + r) * NT] = cc;
             }
+        }
     }
 }
 
@@ -422,7 +440,7 @@ __device__ __forceinline__ void lane_times(const float4* __restrict__ ev32, int 
 
 // The compensation terms of the row sums are touched once per 64 columns, so they live in LDS
 // (one float per thread per accumulator, thread-contiguous) rather than in registers.
-template <bool GRAD>
+template <bool GRAD, bool ZSKIP>
 __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSymWavesPerSimd<GRAD>))) void pair_sym_fp32c(const PairBatch batch)
 {
     constexpr int R = kSymRows;
@@ -448,7 +466,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
     const long long ubeg = u;
     int prio = -1;
     int I = walk.I;
-    int tile = walk.tile;
+    int kw = walk.k;  // position of the current unit among row block I's walked tiles
 
     const float tsh = in_vgpr(rq.tsh), tsl = in_vgpr(rq.tsl), nab = in_vgpr(rq.nab);
     const float nae = in_vgpr(rq.nae), kte = in_vgpr(rq.kte);
@@ -503,6 +521,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
 #pragma unroll
             for (int k = 0; k < K * R; ++k) comp[k * NT] = 0.0f;
         }
+        const int tile = ZSKIP ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
         const int j0 = tile * kTile;
         __syncthreads();
 #pragma unroll
@@ -527,8 +546,27 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
             // per tile instead of being kept live across tiles.
             if (GRAD) lane_times(rq.ev32, lrow0, tsh, tsl, t0h, t0l, ti);
             const int ct[R] = {};  // not read: every column of the tile is causal for every row
-            sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, tsh, tsl, nab,
-                                                 nae, kte, s, comp, colw, red_lds[wave], lane);
+            int far_mode = kFullLow;
+            if (ZSKIP) {
+                // Every pair of the tile is at least `gap` apart in time.
+                const float gap = uniform(t_first - (sj[2 * (kTile - 1)].z + sj[2 * (kTile - 1) + 1].z));
+                const bool no_b = gap >= rq.zero_gap_b, no_e = gap >= rq.zero_gap_e;
+                far_mode = no_b ? (no_e ? kSkip : kFullLowE) : (no_e ? kFullLowB : kFullLow);
+            }
+            if (far_mode == kFullLow)
+                sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, tsh, tsl,
+                                                     nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+            else if (far_mode == kFullLowB)
+                sym_tile_fp32<kFullLowB, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, tsh, tsl,
+                                                      nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+            else if (far_mode == kFullLowE)
+                sym_tile_fp32<kFullLowE, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, tsh, tsl,
+                                                      nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+            else
+#pragma unroll
+                for (int qq = 0; qq < KC; ++qq)
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
         } else {
             // Tiles that straddle the rows' causal counts or their own positions, and causal tiles
             // closer in time to the rows than kNearSpans lane spans (taken by the masked path, whose
@@ -564,9 +602,9 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
                 colpart32[qq * rq.col_stride + cb] = (float)v;
             }
         }
-        if (++tile == TB * (I + 1)) {
+        if (++kw == (ZSKIP ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
             ++I;
-            tile = (rq.zcum && I < rq.row_blocks) ? zero_skip_tiles(rq.zcum, rq.row_blocks)[I] : 0;
+            kw = 0;
         }
     }
     if (cur >= 0) {
@@ -710,7 +748,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const long long ubeg = u;
     int prio = -1;
     int I = walk.I;
-    int tile = walk.tile;
+    int kw = walk.k;  // position of the current unit among row block I's walked tiles
 
     double x[R], y[R], t[R];
     int ct[R];
@@ -746,6 +784,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
                 for (int r = 0; r < R; ++r) a[k][r] = 0.0;
         }
+        const int tile = (rq.zcum != nullptr) ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
         const int j0 = tile * kTile;
         __syncthreads();
         sj[threadIdx.x] = rq.ev64[j0 + threadIdx.x];
@@ -773,9 +812,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int qq = 0; qq < KC; ++qq)
             rq.colpart[qq * rq.col_stride + cb] = colred[0][qq][threadIdx.x] + colred[1][qq][threadIdx.x] +
                                                   colred[2][qq][threadIdx.x] + colred[3][qq][threadIdx.x];
-        if (++tile == TB * (I + 1)) {
+        if (++kw == ((rq.zcum != nullptr) ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
             ++I;
-            tile = (rq.zcum && I < rq.row_blocks) ? zero_skip_tiles(rq.zcum, rq.row_blocks)[I] : 0;
+            kw = 0;
         }
     }
     if (cur >= 0) {
@@ -798,14 +837,19 @@ hipError_t launch_zero_prefix(const PairBatch& b, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme, hipStream_t s)
+hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme, bool zskip, hipStream_t s)
 {
     if (b.total_items <= 0) return hipSuccess;
     const dim3 grid(b.total_items), block(kThreads);
     if (scheme == kSymmetric) {
         if (precision == kFP32C) {
-            if (grad) pair_sym_fp32c<true><<<grid, dim3(kSymThreads), 0, s>>>(b);
-            else pair_sym_fp32c<false><<<grid, dim3(kSymThreads), 0, s>>>(b);
+            if (zskip) {
+                if (grad) pair_sym_fp32c<true, true><<<grid, dim3(kSymThreads), 0, s>>>(b);
+                else pair_sym_fp32c<false, true><<<grid, dim3(kSymThreads), 0, s>>>(b);
+            } else {
+                if (grad) pair_sym_fp32c<true, false><<<grid, dim3(kSymThreads), 0, s>>>(b);
+                else pair_sym_fp32c<false, false><<<grid, dim3(kSymThreads), 0, s>>>(b);
+            }
         } else {
             if (grad) pair_sym_fp64<true><<<grid, block, 0, s>>>(b);
             else pair_sym_fp64<false><<<grid, block, 0, s>>>(b);
@@ -825,8 +869,8 @@ int sym_blocks_per_cu(int precision, bool grad)
     int nb = 0;
     hipError_t e;
     if (precision == kFP32C)
-        e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<true>, kSymThreads, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<false>, kSymThreads, 0);
+        e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<true, false>, kSymThreads, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<false, false>, kSymThreads, 0);
     else
         e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<true>, kThreads, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<false>, kThreads, 0);

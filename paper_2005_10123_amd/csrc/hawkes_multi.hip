@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     const long long ubeg = u;
     int prio = -1;
     int I = walk.I;
-    int tile = walk.tile;
+    int kw = walk.k;  // position of the current unit among row block I's walked tiles
 
     float nab[KT], nbb[KT], nae[KT], nbe[KT];
 #pragma unroll
@@ -203,6 +203,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                     comp[(k * R + r) * kThreads] = 0.0f;
                 }
         }
+        const int tile = (rq.zcum != nullptr) ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
         const int j0 = tile * kTile;
         __syncthreads();
         const float4* src = rq.ev32 + 2 * (size_t)(j0 + threadIdx.x);
@@ -253,9 +254,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int q = 0; q < KT; ++q)
             rq.colpart[q * rq.col_stride + cb] = (double)colred[0][q][threadIdx.x] + (double)colred[1][q][threadIdx.x] +
                                                  (double)colred[2][q][threadIdx.x] + (double)colred[3][q][threadIdx.x];
-        if (++tile == TB * (I + 1)) {
+        if (++kw == ((rq.zcum != nullptr) ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
             ++I;
-            tile = (rq.zcum && I < rq.row_blocks) ? zero_skip_tiles(rq.zcum, rq.row_blocks)[I] : 0;
+            kw = 0;
         }
     }
     if (cur >= 0) {

@@ -105,6 +105,8 @@ size_t scratch_bytes(const Plan& pl, int64_t n, bool rows);
 // Time separation from which a pair's background and trigger exponentials are both exactly zero
 // in the arithmetic of `precision` (zero-tile skipping).
 double zero_separation(const hawkes_params& p, int precision);
+// Its two parts: the separations from which every background / every trigger term is zero.
+void zero_gaps(const hawkes_params& p, int precision, double& background, double& trigger);
 void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const Carved& cv, PairReq& r);
 void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, const Carved& cv,
               EpiReq& e);

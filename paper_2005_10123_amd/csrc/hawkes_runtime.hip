@@ -165,12 +165,18 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
 // arithmetic: the base-2 exponents nbb dt^2 (background) and nbe dt (trigger) are then at most
 // -170, far below binary32's smallest subnormal 2^-149 (FP32C), or at most -1110, where the
 // binary64 exponential is clamped to 2^-1100 = 0 (FP64).  The spatial parts only lower them.
-double zero_separation(const hawkes_params& p, int precision)
+void zero_gaps(const hawkes_params& p, int precision, double& background, double& trigger)
 {
     const double log2e = 1.44269504088896340736;
     const double c = precision == kFP32C ? 170.0 : 1110.0;
-    const double background = p.tau_t * std::sqrt(2.0 * c / log2e);
-    const double trigger = c / (p.omega * log2e);
+    background = p.tau_t * std::sqrt(2.0 * c / log2e);
+    trigger = c / (p.omega * log2e);
+}
+
+double zero_separation(const hawkes_params& p, int precision)
+{
+    double background, trigger;
+    zero_gaps(p, precision, background, trigger);
     return std::max(background, trigger);
 }
 
@@ -193,7 +199,11 @@ void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const C
     r.ubegin = pl.ubegin;
     r.items = pl.items;
     r.zcum = cv.zcum;
-    r.zero_dt = zero_separation(p, pl.precision);
+    double gap_b, gap_e;
+    zero_gaps(p, pl.precision, gap_b, gap_e);
+    r.zero_dt = std::max(gap_b, gap_e);
+    r.zero_gap_b = (float)gap_b;
+    r.zero_gap_e = (float)gap_e;
     fold(p, r);
 }
 
@@ -317,7 +327,7 @@ hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params&
         e = launch_zero_prefix(pb, s);
         if (e != hipSuccess) return hip_fail(e, "zero-tile table launch");
     }
-    e = launch_pair(pb, precision, grad, pl.scheme, s);
+    e = launch_pair(pb, precision, grad, pl.scheme, pl.zskip, s);
     if (e != hipSuccess) return hip_fail(e, "pair kernel launch");
     if (c->profile) {
         e = hipEventRecord(c->prof_ev[1], s);

@@ -251,7 +251,7 @@ void admit(hawkes_ctx* c, Server* sv)
         const bool grad = L.req[0].req.want_grad != 0;
         hipError_t e = hipSuccess;
         if (zero_skip && scheme == kSymmetric) e = launch_zero_prefix(pb, s);
-        if (e == hipSuccess) e = launch_pair(pb, prec, grad, scheme, s);
+        if (e == hipSuccess) e = launch_pair(pb, prec, grad, scheme, zero_skip && scheme == kSymmetric, s);
         if (e == hipSuccess) e = launch_epilogue(eb, s);
         if (e == hipSuccess) e = launch_final(eb, s);
         if (e == hipSuccess) e = hipMemcpyAsync(L.h_out, L.d_out, (size_t)nb * 8 * sizeof(double), hipMemcpyDeviceToHost, s);

@@ -54,7 +54,7 @@ hawkes_status hawkes_shard_sums(hawkes_ctx* c, int32_t id, const hawkes_params* 
         e = hipEventRecord(c->prof_ev[0], s);
         if (e != hipSuccess) return poison(c, hip_fail(e, "hipEventRecord"));
     }
-    e = launch_pair(pb, precision, true, kSymmetric, s);
+    e = launch_pair(pb, precision, true, kSymmetric, false, s);
     if (e != hipSuccess) return poison(c, hip_fail(e, "pair kernel launch"));
     if (c->profile) {
         e = hipEventRecord(c->prof_ev[1], s);

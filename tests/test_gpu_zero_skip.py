@@ -59,17 +59,21 @@ def test_skipping_matches_oracle_and_unskipped(ctx, prec):
     assert np.array_equal(sums_skip, sums)
 
 
-def test_nothing_to_skip_is_bitwise_identical(ctx):
-    """Over 150 days no pair is 307 days apart: the skipping walk is the unskipped one."""
+def test_nothing_to_skip(ctx):
+    """Over 150 days no pair is 236 days apart: every tile is walked (in another order) and every
+    term formed, so the result is the unskipped one up to the order of the row sums."""
     x, y, t = long_window(3000, 150.0, 2)
     ds = ctx.dataset(x, y, t)
     try:
         for prec in ("fp64", "fp32c"):
             ell0, g0 = ctx.grad(ds, THETA, prec)
+            l1 = np.abs(ctx.rows(ds, THETA, prec)["grad"]).sum(axis=0)
             ctx.set_zero_tile_skipping(True)
             ell1, g1 = ctx.grad(ds, THETA, prec)
             ctx.set_zero_tile_skipping(False)
-            assert ell1 == ell0 and np.array_equal(g1, g0), prec
+            tol = 1e-13 if prec == "fp64" else 1e-10
+            assert rel(ell1, ell0) <= tol, (prec, ell1, ell0)
+            assert np.all(np.abs(g1 - g0) <= tol * l1), (prec, g1, g0)
     finally:
         ctx.set_zero_tile_skipping(False)
         ds.close()
