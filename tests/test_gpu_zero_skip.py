@@ -146,3 +146,19 @@ def test_multi_with_skipping_matches_unskipped(ctx):
     ref = oracle.evaluate(x, y, t, th[0], rows=True)
     assert rel(ll1[0], ref["ell"]) <= TOL["fp32c"]
     assert np.max(np.abs(pi1[0] - ref["row_pi"])) <= TOL["fp32c"]
+
+
+def test_direct_enumeration_ignores_skipping(ctx):
+    """Skipping belongs to the symmetric enumeration; the direct one evaluates every pair."""
+    x, y, t = long_window(3000, 5000.0, 7)
+    ds = ctx.dataset(x, y, t)
+    try:
+        ctx.set_pair_scheme("direct")
+        ell0, g0 = ctx.grad(ds, THETA, "fp32c")
+        ctx.set_zero_tile_skipping(True)
+        ell1, g1 = ctx.grad(ds, THETA, "fp32c")
+        assert ell1 == ell0 and np.array_equal(g1, g0)
+    finally:
+        ctx.set_zero_tile_skipping(False)
+        ctx.set_pair_scheme("symmetric")
+        ds.close()
