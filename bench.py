@@ -457,6 +457,12 @@ def main():
             r = serving_run(ctx, seconds=3.0, utilisation=u, min_requests=0)
             result["serving_sweep"].append({k: r[k] for k in ("offered_utilisation", "requests", "p50_ms", "p99_ms",
                                                               "pairs_per_s")})
+        # The same closed loop with zero-tile skipping on (capacity re-estimated with it on).
+        ctx.set_zero_tile_skipping(True)
+        r = serving_run(ctx, seconds=4.0, min_requests=5000)
+        ctx.set_zero_tile_skipping(False)
+        result["serving_zero_tile_skip"] = {k: r[k] for k in ("offered_utilisation", "requests", "p50_ms", "p90_ms",
+                                                               "p99_ms", "pairs_per_s")}
         result["pi_batch"] = pi_batch_run(ctx)
     ctx.close()
     if not args.no_cpu_baseline:
