@@ -440,6 +440,9 @@ __device__ __forceinline__ void lane_times(const float4* __restrict__ ev32, int 
 
 // The compensation terms of the row sums are touched once per 64 columns, so they live in LDS
 // (one float per thread per accumulator, thread-contiguous) rather than in registers.
+// ZSKIP: the variant for zero-tile skipping (PairReq::zcum set): row blocks' walked tiles in the
+// order of walk_tile, and far tiles where one kernel's terms are all exactly zero forming only the
+// other's (modes kFullLowB, kFullLowE).
 template <bool GRAD, bool ZSKIP>
 __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSymWavesPerSimd<GRAD>))) void pair_sym_fp32c(const PairBatch batch)
 {
