@@ -162,3 +162,24 @@ def test_direct_enumeration_ignores_skipping(ctx):
         ctx.set_zero_tile_skipping(False)
         ctx.set_pair_scheme("symmetric")
         ds.close()
+
+
+def test_autograd_with_skipping_matches_blocking(ctx):
+    """The device entry point behind torch.autograd runs the same skipping plan as the blocking call."""
+    import torch
+
+    from paper_2005_10123_amd.autograd import HawkesLogLik
+
+    x, y, t = long_window(6000, 5000.0, 8)
+    ds = ctx.dataset(x, y, t)
+    try:
+        ctx.set_zero_tile_skipping(True)
+        for prec in ("fp64", "fp32c"):
+            theta = torch.tensor(THETA, dtype=torch.float64, requires_grad=True)
+            ell = HawkesLogLik.apply(theta, ctx, ds, prec)
+            ell.backward()
+            ell_b, g_b = ctx.grad(ds, THETA, prec)
+            assert ell.item() == ell_b and np.array_equal(theta.grad.numpy(), g_b), prec
+    finally:
+        ctx.set_zero_tile_skipping(False)
+        ds.close()
