@@ -52,3 +52,23 @@ def test_full_size_fp32c_against_fp64(stress):
     assert np.max(np.abs(r64["lambda"][idx] - ref["lambda"]) / ref["lambda"]) <= TOL["fp64"]
     ds.close()
     ctx.close()
+
+
+def test_full_size_zero_tile_skipping(stress):
+    """At 10^6 events over 20,000 days most tiles are skipped; the per-event results agree with the
+    full pass to rounding and sampled rows with the oracle."""
+    x, y, t, th = stress
+    ctx = binding.Context(0)
+    ds = ctx.dataset(x, y, t)
+    e0, g0 = ctx.grad(ds, th, "fp32c")
+    ctx.set_zero_tile_skipping(True)
+    e1, g1 = ctx.grad(ds, th, "fp32c")
+    r1 = ctx.rows(ds, th, "fp32c")
+    ctx.set_zero_tile_skipping(False)
+    assert rel(e1, e0) <= 1e-12, (e1, e0)
+    assert np.all(np.abs(g1 - g0) <= 1e-12 * np.abs(r1["grad"]).sum(axis=0)), (g1, g0)
+    idx = np.array([0, 1, 250000, 500000, 999998, 999999])
+    ref = oracle.rows(x, y, t, th, idx)
+    assert np.max(np.abs(r1["lambda"][idx] - ref["lambda"]) / ref["lambda"]) <= TOL["fp32c"]
+    ds.close()
+    ctx.close()
