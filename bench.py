@@ -112,7 +112,7 @@ def cpu_baseline(x, y, t, theta, budget_s=12.0):
     a = time.perf_counter()
     oracle.rows(x, y, t, theta, idx)
     sec = time.perf_counter() - a
-    return {"value": m * n / sec, "unit": "pairs/s", "cores": 1, "kind": "oracle",
+    return {"value": m * n / sec, "unit": "pairs/s", "cores": 1, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": f"{m} evenly spaced events (rows) of the {n}-event workload, each against all {n} "
                       f"events, log-likelihood + gradient terms, single-threaded FP64 C; {sec:.1f} s",
             "per_row_s": sec / m}
@@ -136,6 +136,62 @@ def cpu_baseline_threads(x, y, t, theta, per_row_s, budget_s=8.0):
     return {"value": m * n / sec, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"{m} evenly spaced rows of the {n}-event workload against all {n} events, split into "
                       f"{threads} contiguous row ranges run concurrently; {sec:.1f} s"}
+
+
+def cpu_model():
+    """The host CPU's model name (first processor in /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_full_run():
+    """One-off: the FP64 oracle over whole workloads on the host (not part of the default run):
+    the 2,000-event workload, a seeded 20,000-event subsample of the 10^6-event one, and the full
+    85,000-event gradient workload single-threaded and over all host cores (row partitions).
+    Minutes of CPU work."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import oracle
+    from paper_2005_10123_amd import synth
+
+    out = {"cpu_model": cpu_model(), "host_threads": len(os.sched_getaffinity(0)), "runs": []}
+    (x, y, t), th = synth.config_events("small_2k")
+    a = time.perf_counter()
+    oracle.evaluate(x, y, t, th)
+    sec = time.perf_counter() - a
+    out["runs"].append({"workload": "small_2k", "n_events": x.size, "threads": 1, "seconds": sec,
+                        "pairs_per_s": float(x.size) ** 2 / sec})
+    (x, y, t), th = synth.config_events("stress_1m")
+    xs, ys, ts = synth.subsample(x, y, t, 20000)
+    a = time.perf_counter()
+    oracle.evaluate(xs, ys, ts, th)
+    sec = time.perf_counter() - a
+    out["runs"].append({"workload": "stress_1m subsample", "n_events": xs.size, "threads": 1, "seconds": sec,
+                        "pairs_per_s": float(xs.size) ** 2 / sec})
+    (x, y, t), th = synth.config_events("city_85k_10km")
+    n = x.size
+    print(json.dumps({"progress": "city_85k_10km single thread: starting"}), flush=True)
+    a = time.perf_counter()
+    ell, _ = oracle.evaluate(x, y, t, th)
+    sec = time.perf_counter() - a
+    print(json.dumps({"progress": "city_85k_10km single thread", "seconds": sec}), flush=True)
+    out["runs"].append({"workload": "city_85k_10km", "n_events": n, "threads": 1, "seconds": sec,
+                        "pairs_per_s": float(n) ** 2 / sec, "loglik": ell})
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    parts = np.array_split(np.arange(n), threads)
+    with ThreadPoolExecutor(threads) as pool:
+        a = time.perf_counter()
+        list(pool.map(lambda r: oracle.rows(x, y, t, th, r), parts))
+        sec = time.perf_counter() - a
+    out["runs"].append({"workload": "city_85k_10km", "n_events": n, "threads": threads, "seconds": sec,
+                        "pairs_per_s": float(n) ** 2 / sec})
+    return out
 
 
 THETA_POSTERIOR = (1.0, 1.6, 14.0, 0.153, 1440.0, 0.0695)
@@ -397,7 +453,12 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (5 times), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters, then exit")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="only time the FP64 oracle over whole workloads on the host (minutes), then exit")
     args = ap.parse_args()
+    if args.cpu_full:
+        print(json.dumps(cpu_full_run()), flush=True)
+        return
     if args.timing_only:
         args.no_serving = args.no_cpu_baseline = args.no_shards = True
     if args.copy_calibration:
@@ -411,8 +472,9 @@ def main():
         print(json.dumps({"copy_calibration_bytes": src.numel() * 4, "copies": 5}))
         return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the evaluation would shard by rows with one 7-double exchange, not built here)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (one evaluation would "
+              "split the symmetric pass's work units over the devices and add their per-event sums with one "
+              "all-reduce; see hawkes_shard_sums / hawkes_finish, not driven across devices here)", file=sys.stderr)
         sys.exit(2)
 
     import torch
