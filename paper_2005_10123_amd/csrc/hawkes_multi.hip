@@ -278,7 +278,7 @@ __global__ __launch_bounds__(kThreads) void epilogue_multi(const MultiEpi e)
     constexpr long long TB = kRowsPerBlock / kTile;
     __shared__ double red[KT][kThreads];
     const int i = blockIdx.x * kThreads + threadIdx.x;
-    double v[KT] = {0, 0, 0, 0};
+    double v[KT] = {};
     if (i < e.n) {
         const int I = i / kRowsPerBlock, rho = i % kRowsPerBlock;
         long long bf, bl;
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kThreads) void epilogue_multi(const MultiEpi e)
             bf = split_block(TB * I * (I + 1) / 2, e.ubase, e.urem);
             bl = split_block(TB * (I + 1) * (I + 2) / 2 - 1, e.ubase, e.urem);
         }
-        double Sb[KT] = {0, 0, 0, 0}, Se[KT] = {0, 0, 0, 0};
+        double Sb[KT] = {}, Se[KT] = {};
         for (long long b = bf; b <= bl; ++b) {
             const double* ps = e.part + (size_t)(b + I) * 2 * KT * kRowsPerBlock + rho;
 #pragma unroll
@@ -346,7 +346,7 @@ __global__ __launch_bounds__(kThreads) void final_multi(const MultiEpi e)
 {
     constexpr int KT = kMultiTheta;
     __shared__ double red[KT][kThreads];
-    double v[KT] = {0, 0, 0, 0};
+    double v[KT] = {};
     for (int b = threadIdx.x; b < e.nblocks; b += kThreads)
 #pragma unroll
         for (int q = 0; q < KT; ++q) v[q] += e.block_part[(size_t)b * KT + q];
