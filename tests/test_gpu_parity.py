@@ -70,6 +70,20 @@ def test_ties_and_degenerate(ctx):
     check_full(ctx, x, y, t, (1.0, 0.3, 5.0, 0.0, 0.8, 0.2), "theta=0")
 
 
+@pytest.mark.parametrize("theta,what", [
+    ((1.0, 1e-4, 20.0, 0.3, 0.5, 0.1), "tau_x far below the spacing: B is the diagonal alone"),
+    ((1.0, 0.5, 1e6, 0.3, 0.5, 0.1), "tau_t far above the window: B constant in time"),
+    ((1.0, 0.5, 20.0, 0.3, 1e-6, 0.1), "omega tiny: E constant in time"),
+    ((1.0, 0.5, 20.0, 0.3, 0.5, 1e3), "h far above the extent: E constant in space"),
+    ((1e-3, 0.5, 20.0, 5.0, 50.0, 0.01), "trigger-dominated intensity"),
+])
+def test_extreme_valid_parameters(ctx, theta, what):
+    """Bandwidths and rates many orders of magnitude from the data's scales (all inside the domain):
+    both precisions and both enumerations still match the oracle."""
+    (x, y, t), _ = synth.config_events("small_2k", n=1200)
+    check_full(ctx, x, y, t, theta, what)
+
+
 def test_per_event_rows(ctx):
     x, y, t = synth.simulate(synth.SimSpec(1500, 5.0, 300.0, 3, 0.5, 0.1, 0.5, (9, 9, 9)))
     perm = np.random.default_rng(1).permutation(x.size)
