@@ -18,6 +18,13 @@
 namespace hawkes {
 
 constexpr int kMultiTheta = 4;
+// Shape of the FP32C multi-parameter pass: kMultiRows rows per lane; a block's threads together hold
+// one row block of the walk; the register budget is sized for kMultiWavesPerSimd waves per SIMD.
+constexpr int kMultiRows = 4;
+constexpr int kMultiThreads = kRowsPerBlock / kMultiRows;
+constexpr int kMultiWaves = kMultiThreads / 64;
+constexpr int kMultiWavesPerSimd = 2;
+static_assert(kMultiThreads % 64 == 0 && kMultiThreads >= kTile, "multi-parameter block shape");
 
 struct MultiReq {
     const float4* ev32;
@@ -52,17 +59,17 @@ using namespace dev;
 
 template <int MODE>
 __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0, int lrow0,
-                                           const float (&xh)[kRowsPerLane], const float (&yh)[kRowsPerLane],
-                                           const float (&xl)[kRowsPerLane], const float (&yl)[kRowsPerLane],
-                                           const float (&ti)[kRowsPerLane], const float (&th)[kRowsPerLane],
-                                           const float (&tl)[kRowsPerLane], const int (&ct)[kRowsPerLane],
+                                           const float (&xh)[kMultiRows], const float (&yh)[kMultiRows],
+                                           const float (&xl)[kMultiRows], const float (&yl)[kMultiRows],
+                                           const float (&ti)[kMultiRows], const float (&th)[kMultiRows],
+                                           const float (&tl)[kMultiRows], const int (&ct)[kMultiRows],
                                            float t0h, float t0l, const float (&nab)[kMultiTheta],
                                            const float (&nbb)[kMultiTheta], const float (&nae)[kMultiTheta],
-                                           const float (&nbe)[kMultiTheta], float (&s)[2 * kMultiTheta][kRowsPerLane],
+                                           const float (&nbe)[kMultiTheta], float (&s)[2 * kMultiTheta][kMultiRows],
                                            volatile lds_float* comp, float* __restrict__ colw,
                                            float* __restrict__ red, int lane)
 {
-    constexpr int R = kRowsPerLane;
+    constexpr int R = kMultiRows;
     constexpr int KT = kMultiTheta;
     // Far tiles measure times from the lane's first row; masked and near ones take each pair's time
     // difference from the hi/lo parts of both events (see kNearSpans).
@@ -118,23 +125,23 @@ __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0
         for (int k = 0; k < 2 * KT; ++k)
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                float cc = comp[(k * R + r) * kThreads];
+                float cc = comp[(k * R + r) * kMultiThreads];
                 two_sum_into(s[k][r], cc, p[k][r]);
-                comp[(k * R + r) * kThreads] = cc;
+                comp[(k * R + r) * kMultiThreads] = cc;
             }
     }
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void pair_multi_fp32c(const MultiReq rq)
+__global__ __launch_bounds__(kMultiThreads) __attribute__((amdgpu_waves_per_eu(kMultiWavesPerSimd))) void pair_multi_fp32c(const MultiReq rq)
 {
-    constexpr int R = kRowsPerLane;
+    constexpr int R = kMultiRows;
     constexpr int KT = kMultiTheta;
     constexpr int K = 2 * KT;
     constexpr int TB = kRowsPerBlock / kTile;
     __shared__ float4 sj[2 * kTile];
-    __shared__ float colred[4][KT][kTile];
-    __shared__ float comp_lds[K * R * kThreads];
-    __shared__ float red_lds[4][4 * 64];
+    __shared__ float colred[kMultiWaves][KT][kTile];
+    __shared__ float comp_lds[K * R * kMultiThreads];
+    __shared__ float red_lds[kMultiWaves][4 * 64];
     volatile lds_float* comp = (lds_float*)comp_lds + threadIdx.x;
 
     const int blk = (int)blockIdx.x;
@@ -173,7 +180,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
                     for (int r = 0; r < R; ++r)
                         rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
-                            (double)s[k][r] + (double)comp[(k * R + r) * kThreads];
+                            (double)s[k][r] + (double)comp[(k * R + r) * kMultiThreads];
             }
             cur = I;
             w0 = I * kRowsPerBlock + wave * (64 * R);
@@ -200,15 +207,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
                     s[k][r] = 0.0f;
-                    comp[(k * R + r) * kThreads] = 0.0f;
+                    comp[(k * R + r) * kMultiThreads] = 0.0f;
                 }
         }
         const int tile = (rq.zcum != nullptr) ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
         const int j0 = tile * kTile;
         __syncthreads();
-        const float4* src = rq.ev32 + 2 * (size_t)(j0 + threadIdx.x);
-        sj[2 * threadIdx.x] = src[0];
-        sj[2 * threadIdx.x + 1] = src[1];
+        for (int c = threadIdx.x; c < kTile; c += kMultiThreads) {
+            const float4* src = rq.ev32 + 2 * (size_t)(j0 + c);
+            sj[2 * c] = src[0];
+            sj[2 * c + 1] = src[1];
+        }
         __syncthreads();
         int mode;
         if (!active || j0 >= w0 + 64 * R) mode = kSkip;
@@ -249,11 +258,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
                                      colw, red_lds[wave], lane);
         }
         __syncthreads();
-        const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;
+        for (int c = threadIdx.x; c < kTile; c += kMultiThreads) {
+            const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + c;
 #pragma unroll
-        for (int q = 0; q < KT; ++q)
-            rq.colpart[q * rq.col_stride + cb] = (double)colred[0][q][threadIdx.x] + (double)colred[1][q][threadIdx.x] +
-                                                 (double)colred[2][q][threadIdx.x] + (double)colred[3][q][threadIdx.x];
+            for (int q = 0; q < KT; ++q) {
+                double v = 0.0;
+#pragma unroll
+                for (int w = 0; w < kMultiWaves; ++w) v += (double)colred[w][q][c];
+                rq.colpart[q * rq.col_stride + cb] = v;
+            }
+        }
         if (++kw == ((rq.zcum != nullptr) ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
             ++I;
             kw = 0;
@@ -265,7 +279,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
             for (int r = 0; r < R; ++r)
                 rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
-                    (double)s[k][r] + (double)comp[(k * R + r) * kThreads];
+                    (double)s[k][r] + (double)comp[(k * R + r) * kMultiThreads];
     }
 }
 
@@ -369,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void final_multi(const MultiEpi e)
 int multi_blocks_per_cu()
 {
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_multi_fp32c, kThreads, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_multi_fp32c, kMultiThreads, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
@@ -463,7 +477,7 @@ static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_p
             err = launch_zero_prefix(zb, s);
             if (err != hipSuccess) break;
         }
-        pair_multi_fp32c<<<dim3(items), dim3(kThreads), 0, s>>>(r);
+        pair_multi_fp32c<<<dim3(items), dim3(kMultiThreads), 0, s>>>(r);
         epilogue_multi<<<dim3(nblocks), dim3(kThreads), 0, s>>>(e);
         final_multi<<<dim3(1), dim3(kThreads), 0, s>>>(e);
         err = hipGetLastError();
