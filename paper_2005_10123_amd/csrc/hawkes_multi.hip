@@ -472,7 +472,7 @@ static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_p
         }
         if (zero_skip) {
             double zdt = 0.0;
-            for (int q = 0; q < nth; ++q) zdt = std::max(zdt, zero_separation(th[s0 + q], kFP32C));
+            for (int q = 0; q < nth; ++q) zdt = std::max(zdt, zero_separation(th[s0 + q], kFP32C, d.T));
             zb.r[0].zero_dt = zdt;
             err = launch_zero_prefix(zb, s);
             if (err != hipSuccess) break;

@@ -104,9 +104,10 @@ Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precisio
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows);
 // Time separation from which a pair's background and trigger exponentials are both exactly zero
 // in the arithmetic of `precision` (zero-tile skipping).
-double zero_separation(const hawkes_params& p, int precision);
+// T: the dataset's largest time (for the binary32 rounding of the FP32C pass's times).
+double zero_separation(const hawkes_params& p, int precision, double T);
 // Its two parts: the separations from which every background / every trigger term is zero.
-void zero_gaps(const hawkes_params& p, int precision, double& background, double& trigger);
+void zero_gaps(const hawkes_params& p, int precision, double T, double& background, double& trigger);
 void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const Carved& cv, PairReq& r);
 void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, const Carved& cv,
               EpiReq& e);

@@ -165,18 +165,27 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
 // arithmetic: the base-2 exponents nbb dt^2 (background) and nbe dt (trigger) are then at most
 // -170, far below binary32's smallest subnormal 2^-149 (FP32C), or at most -1110, where the
 // binary64 exponential is clamped to 2^-1100 = 0 (FP64).  The spatial parts only lower them.
-void zero_gaps(const hawkes_params& p, int precision, double& background, double& trigger)
+void zero_gaps(const hawkes_params& p, int precision, double T, double& background, double& trigger)
 {
     const double log2e = 1.44269504088896340736;
     const double c = precision == kFP32C ? 170.0 : 1110.0;
     background = p.tau_t * std::sqrt(2.0 * c / log2e);
     trigger = c / (p.omega * log2e);
+    if (precision == kFP32C) {
+        // The FP32C pass forms time differences from binary32 times (centred, |t - centre| <=
+        // T / 2) and its kernel compares a binary32 gap with these: widen them by far more than
+        // those roundings can move a difference, so every term left out would have been exactly
+        // zero in that arithmetic too.
+        const double widen = 1.0 + std::ldexp(1.0, -18), slack = std::ldexp(T, -18);
+        background = background * widen + slack;
+        trigger = trigger * widen + slack;
+    }
 }
 
-double zero_separation(const hawkes_params& p, int precision)
+double zero_separation(const hawkes_params& p, int precision, double T)
 {
     double background, trigger;
-    zero_gaps(p, precision, background, trigger);
+    zero_gaps(p, precision, T, background, trigger);
     return std::max(background, trigger);
 }
 
@@ -200,7 +209,7 @@ void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const C
     r.items = pl.items;
     r.zcum = cv.zcum;
     double gap_b, gap_e;
-    zero_gaps(p, pl.precision, gap_b, gap_e);
+    zero_gaps(p, pl.precision, d.T, gap_b, gap_e);
     r.zero_dt = std::max(gap_b, gap_e);
     r.zero_gap_b = (float)gap_b;
     r.zero_gap_e = (float)gap_e;
