@@ -511,7 +511,7 @@ def main():
         "data": "synthetic: seeded branching (Hawkes cluster) simulation, 3-component Gaussian-mixture background",
         "config": {"workload": f"{args.workload}: N={n} events, 10x10 km, 1000 days; theta=(mu0, tau_x, tau_t, "
                                f"theta, omega, h)={tuple(theta)}; fused log-likelihood + gradient, FP32-compensated",
-                   "n_events": n, "pairs_per_step": pairs},
+                   "n_events": n, "pairs_per_step": pairs, "zero_tile_skipping": False},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": roof / 1e9, "unit": "Gpair/s",
                      "frac": achieved / roof,
                      "traffic": measured_traffic(os.path.join(ROOT, "profiles", "pair_sym_fp32c_grad_city85k.json")),
