@@ -482,6 +482,7 @@ def main():
     from paper_2005_10123_amd import binding, synth
 
     (x, y, t), theta = synth.config_events(args.workload)
+    spec = synth.CONFIGS[args.workload][0]
     n = x.size
     ctx = binding.Context(0)
     ds = ctx.dataset(x, y, t)
@@ -509,8 +510,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32c",
         "data": "synthetic: seeded branching (Hawkes cluster) simulation, 3-component Gaussian-mixture background",
-        "config": {"workload": f"{args.workload}: N={n} events, 10x10 km, 1000 days; theta=(mu0, tau_x, tau_t, "
-                               f"theta, omega, h)={tuple(theta)}; fused log-likelihood + gradient, FP32-compensated",
+        "config": {"workload": f"{args.workload}: N={n} events, {spec.L:g}x{spec.L:g} km, {spec.T_end:g} days; "
+                               f"theta=(mu0, tau_x, tau_t, theta, omega, h)={tuple(theta)}; fused log-likelihood + "
+                               f"gradient, FP32-compensated",
                    "n_events": n, "pairs_per_step": pairs, "zero_tile_skipping": False},
         "roofline": {"bound": "alu", "achieved": achieved / 1e9, "peak": roof / 1e9, "unit": "Gpair/s",
                      "frac": achieved / roof,
