@@ -402,7 +402,10 @@ hawkes_status hawkes_poll(hawkes_ctx* c, hawkes_result* out, int32_t cap, int32_
     }
     sv->outstanding -= k;
     *n_out = k;
-    if (k == 0) return fail(HAWKES_EAGAIN, "no completed request");
+    if (k == 0) {
+        g_last_error = "no completed request";  // an ordinary outcome: not logged as a failure
+        return HAWKES_EAGAIN;
+    }
     return HAWKES_OK;
 }
 
