@@ -1,0 +1,51 @@
+"""Host-side pieces of bench.py: the provenance of the reported HBM traffic (a profile record counts
+only while the kernel code it was taken on is unchanged) and the refusal of several GPUs.  CPU only."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+RECORD = os.path.join(ROOT, "profiles", "pair_sym_fp32c_grad_city85k.json")
+
+
+def test_committed_traffic_record_matches_the_kernel_sources():
+    rec = json.load(open(RECORD))
+    assert rec["kernel_source_sha256"] == bench.kernel_source_sha256()
+    assert bench.measured_traffic(RECORD) == rec["fetch_bytes"] + rec["write_bytes"] > 0
+
+
+def test_traffic_is_dropped_when_the_code_changes(tmp_path):
+    rec = json.load(open(RECORD))
+    rec["kernel_source_sha256"] = "0" * 64
+    stale = tmp_path / "stale.json"
+    stale.write_text(json.dumps(rec))
+    assert bench.measured_traffic(str(stale)) is None
+    assert bench.measured_traffic(str(tmp_path / "missing.json")) is None
+
+
+def test_hash_ignores_comments_only(tmp_path, monkeypatch):
+    """Editing a comment keeps the hash; editing code changes it."""
+    src = os.path.join(ROOT, "paper_2005_10123_amd", "csrc")
+    for name in bench.KERNEL_SOURCES:
+        (tmp_path / name).write_text(open(os.path.join(src, name)).read())
+    fake_root = tmp_path / "root"
+    (fake_root / "paper_2005_10123_amd").mkdir(parents=True)
+    os.symlink(tmp_path, fake_root / "paper_2005_10123_amd" / "csrc")
+    monkeypatch.setattr(bench, "ROOT", str(fake_root))
+    base = bench.kernel_source_sha256()
+    assert base == json.load(open(RECORD))["kernel_source_sha256"]
+    k = tmp_path / bench.KERNEL_SOURCES[0]
+    k.write_text(k.read_text() + "\n// a trailing comment\n/* and a block\n   comment */\n")
+    assert bench.kernel_source_sha256() == base
+    k.write_text(k.read_text() + "\nstatic int extra_symbol = 1;\n")
+    assert bench.kernel_source_sha256() != base
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stderr
