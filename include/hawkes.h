@@ -203,13 +203,15 @@ hawkes_status hawkes_set_pair_scheme(hawkes_ctx* ctx, int scheme);
  * for HAWKES_FP32C, binary64 ones below 2^-1110 for HAWKES_FP64), so the pairs further apart add
  * nothing to any sum.  With skipping on, the symmetric enumeration leaves out every column tile
  * whose events all lie at least D before the first event of the row block against which it would
- * be evaluated; on data spanning many multiples of tau_t and 1/omega most pairs are such.  The
+ * be evaluated, and the direct enumeration every tile all of whose events are at least D before or
+ * after all of the row block's; on data spanning many multiples of tau_t and 1/omega most pairs
+ * are such.  The
  * result is the same sum of the same non-zero terms; only its grouping into partial sums changes
  * (as it does with the device's number of compute units), so it agrees with the unskipped
  * evaluation to rounding.  Applies to hawkes_loglik, hawkes_grad, hawkes_grad_device, hawkes_rows,
  * hawkes_loglik_multi (a tile is left out when the terms of every parameter vector of its pass
- * vanish there) and submitted requests made after the call, with the symmetric enumeration; not
- * to hawkes_shard_sums. */
+ * vanish there) and submitted requests made after the call, with either enumeration; not to
+ * hawkes_shard_sums. */
 hawkes_status hawkes_set_zero_tile_skipping(hawkes_ctx* ctx, int enable);
 
 /* ---- diagnostics -------------------------------------------------------------------------- */

@@ -64,6 +64,7 @@ struct PairReq {
     // last event.  Filled by the zero_prefix kernel.
     long long* zcum;
     double zero_dt;
+    int zdirect;  // direct enumeration: walk only the column tiles within zero_dt of the row block
     // With zcum set, the FP32C pass also drops one kernel on far tiles at least zero_gap_b (every
     // background term zero) or zero_gap_e (every trigger term zero) time units before the rows.
     float zero_gap_b, zero_gap_e;

@@ -91,6 +91,44 @@ __device__ __forceinline__ void chunk_fp32(const float4* __restrict__ sj, int jb
     }
 }
 
+// Column tiles [t0, t1) walked by split sp of row block rb in the direct enumeration: all tiles
+// cut into ranges of tiles_per_split; with zero-tile skipping (zdirect), only the tiles that hold an
+// event less than zero_dt from one of the row block's events (a window, the events being
+// time-sorted; tiles of padding only are left out too), cut into `splits` near-equal ranges.
+__device__ __forceinline__ void direct_range(const PairReq& rq, int rb, int sp, int& t0, int& t1)
+{
+    const int tiles = rq.npad / kTile;
+    if (!rq.zdirect) {
+        t0 = sp * rq.tiles_per_split;
+        t1 = min(t0 + rq.tiles_per_split, tiles);
+        return;
+    }
+    const int n = rq.n;
+    const double t_first = rq.ev64[(size_t)rb * kRowsPerBlock].z;
+    const double t_last = rq.ev64[(size_t)min(rb * kRowsPerBlock + kRowsPerBlock - 1, n - 1)].z;
+    // lo: whole tiles ending at least zero_dt before the row block's first event.
+    int lo = 0, hi = n / kTile;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (t_first - rq.ev64[(size_t)mid * kTile + kTile - 1].z >= rq.zero_dt)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    // end: the first tile starting at least zero_dt after the row block's last event.
+    int a = lo, end = (n + kTile - 1) / kTile;
+    while (a < end) {
+        const int mid = (a + end) >> 1;
+        if (rq.ev64[(size_t)mid * kTile].z - t_last >= rq.zero_dt)
+            end = mid;
+        else
+            a = mid + 1;
+    }
+    const long long len = end - lo;
+    t0 = lo + (int)(len * sp / rq.splits);
+    t1 = lo + (int)(len * (sp + 1) / rq.splits);
+}
+
 template <bool GRAD>
 __global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
 {
@@ -145,9 +183,8 @@ __global__ __launch_bounds__(kThreads) void pair_fp32c(const PairBatch batch)
 #pragma unroll
         for (int r = 0; r < R; ++r) s[k][r] = c[k][r] = 0.0f;
 
-    const int tiles = rq.npad / kTile;
-    const int t0 = sp * rq.tiles_per_split;
-    const int t1 = min(t0 + rq.tiles_per_split, tiles);
+    int t0, t1;
+    direct_range(rq, rb, sp, t0, t1);
     for (int tile = t0; tile < t1; ++tile) {
         const int j0 = tile * kTile;
         __syncthreads();
@@ -262,9 +299,8 @@ __global__ __launch_bounds__(kThreads) void pair_fp64(const PairBatch batch)
 #pragma unroll
         for (int r = 0; r < R; ++r) a[k][r] = 0.0;
 
-    const int tiles = rq.npad / kTile;
-    const int t0 = sp * rq.tiles_per_split;
-    const int t1 = min(t0 + rq.tiles_per_split, tiles);
+    int t0, t1;
+    direct_range(rq, rb, sp, t0, t1);
     for (int tile = t0; tile < t1; ++tile) {
         const int j0 = tile * kTile;
         __syncthreads();

@@ -45,6 +45,7 @@ struct Plan {
     size_t part_doubles = 0;  // row partial sums
     size_t col_doubles = 0;   // symmetric: column partial sums
     bool zskip = false;       // symmetric: zero-tile skipping (tables zcum, zskip in the scratch)
+    bool zdirect = false;     // direct: zero-tile skipping (each row block walks its window only)
     size_t zbytes = 0;        // bytes of those tables
 };
 
@@ -98,7 +99,7 @@ hawkes_status hip_fail(hipError_t e, const char* what);
 hawkes_status check_params(const hawkes_params* p);
 // shard / nshards: the evaluation walks the shard-th of nshards contiguous, equal ranges of the
 // symmetric work units (symmetric scheme only; 0 / 1 is the whole triangle).  zero_skip: leave out
-// the column tiles whose pair terms are all exactly zero (symmetric scheme, whole triangle only).
+// the column tiles whose pair terms are all exactly zero (the whole evaluation only, not a shard).
 Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precision, int scheme, int shard = 0,
                int nshards = 1, bool zero_skip = false);
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows);

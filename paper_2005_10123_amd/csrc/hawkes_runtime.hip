@@ -94,6 +94,7 @@ Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precisio
     pl.splits = (tiles + pl.tiles_per_split - 1) / pl.tiles_per_split;
     pl.items = pl.row_blocks * pl.splits;
     pl.part_doubles = (size_t)pl.splits * pl.K * npad;
+    pl.zdirect = zero_skip && shard == 0 && nshards == 1;
     return pl;
 }
 
@@ -208,6 +209,7 @@ void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const C
     r.ubegin = pl.ubegin;
     r.items = pl.items;
     r.zcum = cv.zcum;
+    r.zdirect = pl.zdirect ? 1 : 0;
     double gap_b, gap_e;
     zero_gaps(p, pl.precision, d.T, gap_b, gap_e);
     r.zero_dt = std::max(gap_b, gap_e);

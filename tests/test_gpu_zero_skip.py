@@ -148,20 +148,48 @@ def test_multi_with_skipping_matches_unskipped(ctx):
     assert np.max(np.abs(pi1[0] - ref["row_pi"])) <= TOL["fp32c"]
 
 
-def test_direct_enumeration_ignores_skipping(ctx):
-    """Skipping belongs to the symmetric enumeration; the direct one evaluates every pair."""
-    x, y, t = long_window(3000, 5000.0, 7)
+def test_direct_enumeration_skips_outside_the_window(ctx):
+    """The direct enumeration walks, per row block, only the tiles within the separation on either
+    side: same result to rounding, matching the oracle, and a faster pass."""
+    x, y, t = long_window(6000, 5000.0, 7)
+    ref = oracle.evaluate(x, y, t, THETA, rows=True)
     ds = ctx.dataset(x, y, t)
     try:
         ctx.set_pair_scheme("direct")
-        ell0, g0 = ctx.grad(ds, THETA, "fp32c")
-        ctx.set_zero_tile_skipping(True)
-        ell1, g1 = ctx.grad(ds, THETA, "fp32c")
-        assert ell1 == ell0 and np.array_equal(g1, g0)
+        for prec in ("fp64", "fp32c"):
+            ell0, g0 = ctx.grad(ds, THETA, prec)
+            ctx.set_zero_tile_skipping(True)
+            ell1, g1 = ctx.grad(ds, THETA, prec)
+            ctx.set_zero_tile_skipping(False)
+            assert_close(ell1, g1, ref, prec, "direct, zero-tile skipping", THETA)
+            tol = 1e-13 if prec == "fp64" else 1e-10
+            assert rel(ell1, ell0) <= tol, (prec, ell1, ell0)
+            assert np.all(np.abs(g1 - g0) <= tol * np.abs(ref["row_grad"]).sum(axis=0)), (prec, g1, g0)
     finally:
         ctx.set_zero_tile_skipping(False)
         ctx.set_pair_scheme("symmetric")
         ds.close()
+    x, y, t = long_window(40000, 5000.0, 9)
+    ds = ctx.dataset(x, y, t)
+    times = {}
+    try:
+        ctx.set_pair_scheme("direct")
+        for skip in (False, True):
+            ctx.set_zero_tile_skipping(skip)
+            ctx.grad(ds, THETA, "fp32c")
+            ctx.kernel_time(reset=True)
+            ctx.profile(True)
+            for _ in range(3):
+                ctx.grad(ds, THETA, "fp32c")
+            ms, k = ctx.kernel_time(reset=True)
+            ctx.profile(False)
+            times[skip] = ms / k
+    finally:
+        ctx.set_zero_tile_skipping(False)
+        ctx.set_pair_scheme("symmetric")
+        ds.close()
+    print("direct pass ms without / with skipping:", times[False], times[True])
+    assert times[True] <= 0.5 * times[False], times
 
 
 def test_autograd_with_skipping_matches_blocking(ctx):
