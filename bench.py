@@ -245,24 +245,25 @@ def zero_skip_run(ctx, steps=10):
     memory-linear fallback for data whose triangle does not fit)."""
     from paper_2005_10123_amd import synth
 
-    cases = [("city_85k_10km", None, True, "symmetric"), ("city_85k_15km", None, False, "symmetric"),
-             ("city_85k_15km", THETA_POSTERIOR, True, "symmetric"), ("stress_1m", None, True, "symmetric"),
-             ("stress_1m", None, True, "direct")]
+    cases = [("city_85k_10km", None, True, "symmetric", "fp32c"), ("city_85k_15km", None, False, "symmetric", "fp32c"),
+             ("city_85k_15km", THETA_POSTERIOR, True, "symmetric", "fp32c"),
+             ("city_85k_15km", THETA_POSTERIOR, True, "symmetric", "fp64"),
+             ("stress_1m", None, True, "symmetric", "fp32c"), ("stress_1m", None, True, "direct", "fp32c")]
     out = []
-    for workload, theta_override, grad, scheme in cases:
+    for workload, theta_override, grad, scheme, prec in cases:
         n_steps = 3 if workload == "stress_1m" else steps
         (x, y, t), theta = synth.config_events(workload)
         if theta_override is not None:
             theta = theta_override
         n = x.size
         ds = ctx.dataset(x, y, t)
-        rec = {"workload": workload, "theta": list(theta), "gradient": grad, "precision": "fp32c",
+        rec = {"workload": workload, "theta": list(theta), "gradient": grad, "precision": prec,
                "enumeration": scheme}
         ctx.set_pair_scheme(scheme)
         res = {}
         for skip in (False, True):
             ctx.set_zero_tile_skipping(skip)
-            r, wall, _, kms = time_steps(ctx, ds, theta, "fp32c", grad, n_steps, 1)
+            r, wall, _, kms = time_steps(ctx, ds, theta, prec, grad, n_steps, 1)
             res[skip] = r
             rec["skip" if skip else "all_pairs"] = {"ms_per_call": wall / n_steps * 1e3, "kernel_ms": kms,
                                                     "pairs_per_s": float(n) * n * n_steps / wall}

@@ -716,6 +716,14 @@ __device__ __forceinline__ void sym_tile_fp64(const double4* __restrict__ sj, in
 {
     constexpr int R = kRowsPerLane;
     constexpr int KC = GRAD ? 3 : 1;
+    constexpr bool FAR = MODE == kFullLow || MODE == kFullLowB || MODE == kFullLowE;  // unmasked
+    constexpr bool DO_B = MODE != kFullLowE;  // background terms (and the column sums)
+    constexpr bool DO_E = MODE != kFullLowB;  // trigger terms
+    if (!DO_B)
+#pragma unroll
+        for (int qq = 0; qq < KC; ++qq)
+#pragma unroll
+            for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0;
 #pragma unroll 1
     for (int g = 0; g < kTile; g += 4) {
         double cp[3][4];
@@ -733,38 +741,44 @@ __device__ __forceinline__ void sym_tile_fp64(const double4* __restrict__ sj, in
                 const double dy = y[r] - e.y;
                 const double dt = t[r] - e.z;
                 const double r2 = fma(dx, dx, dy * dy);
-                const double dt2 = dt * dt;
-                double ab = fma(r2, nab, dt2 * nbb);
-                if (MODE == kDiag) ab = (j < lrow0 + r) ? ab : -INFINITY;
-                const double b = exp2_f64(ab);
-                a[0][r] += b;
-                cp[0][cc] += b;
-                if (GRAD) {
-                    a[1][r] = fma(r2, b, a[1][r]);
-                    a[2][r] = fma(dt2, b, a[2][r]);
-                    cp[1][cc] = fma(r2, b, cp[1][cc]);
-                    cp[2][cc] = fma(dt2, b, cp[2][cc]);
+                if (DO_B) {
+                    const double dt2 = dt * dt;
+                    double ab = fma(r2, nab, dt2 * nbb);
+                    if (MODE == kDiag) ab = (j < lrow0 + r) ? ab : -INFINITY;
+                    const double b = exp2_f64(ab);
+                    a[0][r] += b;
+                    cp[0][cc] += b;
+                    if (GRAD) {
+                        a[1][r] = fma(r2, b, a[1][r]);
+                        a[2][r] = fma(dt2, b, a[2][r]);
+                        cp[1][cc] = fma(r2, b, cp[1][cc]);
+                        cp[2][cc] = fma(dt2, b, cp[2][cc]);
+                    }
                 }
-                double ae = fma(r2, nae, dt * nbe);
-                if (MODE != kFullLow) ae = (j < ct[r]) ? ae : -INFINITY;
-                const double ex = exp2_f64(ae);
-                const int ke = GRAD ? 3 : 1;
-                a[ke][r] += ex;
-                if (GRAD) {
-                    a[4][r] = fma(dt, ex, a[4][r]);
-                    a[5][r] = fma(r2, ex, a[5][r]);
+                if (DO_E) {
+                    double ae = fma(r2, nae, dt * nbe);
+                    if (!FAR) ae = (j < ct[r]) ? ae : -INFINITY;
+                    const double ex = exp2_f64(ae);
+                    const int ke = GRAD ? 3 : 1;
+                    a[ke][r] += ex;
+                    if (GRAD) {
+                        a[4][r] = fma(dt, ex, a[4][r]);
+                        a[5][r] = fma(r2, ex, a[5][r]);
+                    }
                 }
             }
         }
-        double v[3];
-        column_sums4<KC>(cp, red, lane, v);
-        if ((lane & 15) == 0)
+        if (DO_B) {
+            double v[3];
+            column_sums4<KC>(cp, red, lane, v);
+            if ((lane & 15) == 0)
 #pragma unroll
-            for (int q = 0; q < KC; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
+                for (int q = 0; q < KC; ++q) colw[q * kTile + g + (lane >> 4)] = v[q];
+        }
     }
 }
 
-template <bool GRAD>
+template <bool GRAD, bool ZSKIP>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) void pair_sym_fp64(const PairBatch batch)
 {
     constexpr int R = kRowsPerLane;
@@ -823,7 +837,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
                 for (int r = 0; r < R; ++r) a[k][r] = 0.0;
         }
-        const int tile = (rq.zcum != nullptr) ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
+        const int tile = ZSKIP ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
         const int j0 = tile * kTile;
         __syncthreads();
         sj[threadIdx.x] = rq.ev64[j0 + threadIdx.x];
@@ -839,7 +853,27 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0;
         } else if (mode == kFullLow) {
-            sym_tile_fp64<kFullLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, red_lds[wave], lane);
+            int far_mode = kFullLow;
+            if (ZSKIP) {
+                // Every pair of the tile is at least `gap` apart in time.
+                const double gap = uniform(rq.ev64[min(w0, n - 1)].z - sj[kTile - 1].z);
+                const bool no_b = gap >= (double)rq.zero_gap_b, no_e = gap >= (double)rq.zero_gap_e;
+                far_mode = no_b ? (no_e ? kSkip : kFullLowE) : (no_e ? kFullLowB : kFullLow);
+            }
+            if (far_mode == kFullLow)
+                sym_tile_fp64<kFullLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw,
+                                              red_lds[wave], lane);
+            else if (far_mode == kFullLowB)
+                sym_tile_fp64<kFullLowB, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw,
+                                               red_lds[wave], lane);
+            else if (far_mode == kFullLowE)
+                sym_tile_fp64<kFullLowE, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw,
+                                               red_lds[wave], lane);
+            else
+#pragma unroll
+                for (int qq = 0; qq < KC; ++qq)
+#pragma unroll
+                    for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0;
         } else if (mode == kMaskLow) {
             sym_tile_fp64<kMaskLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, red_lds[wave], lane);
         } else {
@@ -851,7 +885,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
         for (int qq = 0; qq < KC; ++qq)
             rq.colpart[qq * rq.col_stride + cb] = colred[0][qq][threadIdx.x] + colred[1][qq][threadIdx.x] +
                                                   colred[2][qq][threadIdx.x] + colred[3][qq][threadIdx.x];
-        if (++kw == ((rq.zcum != nullptr) ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
+        if (++kw == (ZSKIP ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
             ++I;
             kw = 0;
         }
@@ -889,9 +923,12 @@ hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme,
                 if (grad) pair_sym_fp32c<true, false><<<grid, dim3(kSymThreads), 0, s>>>(b);
                 else pair_sym_fp32c<false, false><<<grid, dim3(kSymThreads), 0, s>>>(b);
             }
+        } else if (zskip) {
+            if (grad) pair_sym_fp64<true, true><<<grid, block, 0, s>>>(b);
+            else pair_sym_fp64<false, true><<<grid, block, 0, s>>>(b);
         } else {
-            if (grad) pair_sym_fp64<true><<<grid, block, 0, s>>>(b);
-            else pair_sym_fp64<false><<<grid, block, 0, s>>>(b);
+            if (grad) pair_sym_fp64<true, false><<<grid, block, 0, s>>>(b);
+            else pair_sym_fp64<false, false><<<grid, block, 0, s>>>(b);
         }
     } else if (precision == kFP32C) {
         if (grad) pair_fp32c<true><<<grid, block, 0, s>>>(b);
@@ -911,8 +948,8 @@ int sym_blocks_per_cu(int precision, bool grad)
         e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<true, false>, kSymThreads, 0)
                  : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp32c<false, false>, kSymThreads, 0);
     else
-        e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<true>, kThreads, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<false>, kThreads, 0);
+        e = grad ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<true, false>, kThreads, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_sym_fp64<false, false>, kThreads, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
