@@ -230,7 +230,9 @@ def loglik_workload(ctx, steps=10):
     ell = {}
     for prec in ("fp32c", "fp64"):
         ell[prec], wall, _, kms = time_steps(ctx, ds, theta, prec, False, steps, 2)
-        out[prec] = {"ms_per_call": wall / steps * 1e3, "kernel_ms": kms, "pairs_per_s": float(n) * n * steps / wall}
+        out[prec] = {"ms_per_call": wall / steps * 1e3, "kernel_ms": kms, "pairs_per_s": float(n) * n * steps / wall,
+                     # the pairwise kernel against the log-likelihood roofline of the method's work
+                     "roofline_frac": float(n) * n / (kms * 1e-3) / roofline_pairs(False, prec == "fp64")}
     ds.close()
     out["ell_rel_fp32c_vs_fp64"] = abs(ell["fp32c"] - ell["fp64"]) / abs(ell["fp64"])
     return out
