@@ -113,6 +113,26 @@ __device__ __forceinline__ bool far_tile(const float4* __restrict__ sj, float t_
     return uniform(t_first - t_last) >= kNearSpans * span;
 }
 
+// The symmetric FP32C pass measures far tiles' times from the staged tile's first event instead:
+// a column's time since that event (scaled, formed once when the tile is staged and kept in the
+// otherwise unused .w of its hi part) serves every row of the block, and a row's time since it is
+// formed once per tile.  With u the binary32 unit roundoff, S the tile's span and d a pair's
+// difference, the computed difference is off by at most about u (3 d + 4 S): the rounding of each
+// time since the origin and of their difference.  Tiles at least kNearTiles tile spans before the
+// wave's first row (S <= d / 2) keep it within 5 u d; nearer ones take the exact path.  (A wider
+// near zone, 8 tile spans, puts ~5 % of the tiles at N = 85,000 over 1,000 days on the masked path,
+// whose tiles gather at the end of each row block, and was measured 7 % slower.)
+constexpr float kNearTiles = 2.0f;
+
+// Whether a causal tile staged in LDS lies at least kNearTiles of its own spans before the wave's
+// first row (t_first: its centred time, hi + lo).  Uniform over the wave.
+__device__ __forceinline__ bool far_tile_by_span(const float4* __restrict__ sj, float t_first)
+{
+    const float t_origin = sj[0].z + sj[1].z;
+    const float t_last = sj[2 * (kTile - 1)].z + sj[2 * (kTile - 1) + 1].z;
+    return uniform(t_first - t_last) >= kNearTiles * uniform(t_last - t_origin);
+}
+
 // Lane-rotated copy of v within each 16-lane row (DPP control CTRL, e.g. 0x128 = row_ror:8).
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v)

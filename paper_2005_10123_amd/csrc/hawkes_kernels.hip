@@ -345,15 +345,14 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
                                               const float (&xh)[R], const float (&yh)[R],
                                               const float (&xl)[R], const float (&yl)[R],
                                               const float (&ti)[R], const float (&th)[R], const float (&tl)[R],
-                                              const int (&ct)[R],
-                                              float t0h, float t0l, float tsh, float tsl, float nab, float nae,
+                                              const int (&ct)[R], float tsh, float tsl, float nab, float nae,
                                               float kte, float (&s)[6][R], volatile lds_float* comp,
                                               float* __restrict__ colw, float* __restrict__ red, int lane)
 {
     constexpr int K = GRAD ? 6 : 2;
     constexpr int KC = GRAD ? 3 : 1;
-    // Tiles far before the rows measure times from the lane's first row; the others take every
-    // time difference from the hi/lo parts of the two events.
+    // Tiles far before the rows measure times from the tile's first event (rows: ti; columns: the
+    // staged .w); the others take every time difference from the hi/lo parts of the two events.
     constexpr bool FAR = MODE == kFullLow || MODE == kFullLowB || MODE == kFullLowE;
     constexpr bool EXACT = !FAR;
     constexpr bool DO_B = MODE != kFullLowE;  // background terms (and the column sums)
@@ -380,11 +379,7 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
             for (int cc = 0; cc < 4; ++cc) {
                 const float4 hi = sj[2 * (g + cc)];
                 const float4 lo = sj[2 * (g + cc) + 1];
-                float tj = 0.0f;
-                if (!EXACT) {
-                    const float tu = (hi.z - t0h) + (lo.z - t0l);
-                    tj = fmaf(tu, tsh, tu * tsl);
-                }
+                const float tj = EXACT ? 0.0f : hi.w;
                 const int j = j0 + g + cc;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
@@ -459,17 +454,15 @@ template <bool GRAD>
 constexpr int kSymWavesPerSimd = GRAD ? 3 : 4;
 static_assert(kSymThreads % 64 == 0 && kTile % kSymThreads == 0, "symmetric FP32C block shape");
 
-// A lane's row times measured from its first row and scaled by s = tsh + tsl (see the direct
-// pass above), and that origin.
+// The rows' times (hi th, lo tl) since the staged tile's first event (hi c0h, lo c0l), scaled by
+// s = tsh + tsl like the columns' staged times.
 template <int R>
-__device__ __forceinline__ void lane_times(const float4* __restrict__ ev32, int lrow0, float tsh, float tsl,
-                                           float& t0h, float& t0l, float (&ti)[R])
+__device__ __forceinline__ void tile_times(const float (&th)[R], const float (&tl)[R], float c0h, float c0l,
+                                           float tsh, float tsl, float (&ti)[R])
 {
-    t0h = ev32[2 * (size_t)lrow0].z;
-    t0l = ev32[2 * (size_t)lrow0 + 1].z;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-        const float tu = (ev32[2 * (size_t)(lrow0 + r)].z - t0h) + (ev32[2 * (size_t)(lrow0 + r) + 1].z - t0l);
+        const float tu = (th[r] - c0h) + (tl[r] - c0l);
         ti[r] = fmaf(tu, tsh, tu * tsl);
     }
 }
@@ -514,9 +507,8 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
     int cur = -1, w0 = 0, lrow0 = 0, clo = 0;
     bool active = false;
     float t_first = 0.0f;  // centred time of the wave's first row
-    float span = 0.0f;     // largest time spanned by one lane's rows in the wave
-    float ti[R], t0h = 0.0f, t0l = 0.0f;  // lane-origin row times (kept across tiles without the gradient)
-    float th[R], tl[R];                   // the rows' hi/lo times (likewise)
+    float ti[R];           // the rows' times since the current far tile's first event
+    float th[R], tl[R];    // the rows' hi/lo times (kept across tiles without the gradient)
 
     for (; u < uend; ++u) {
         if (rq.balance) progress_priority(u - ubeg, uend - ubeg, prio);
@@ -533,24 +525,15 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
             w0 = I * kRowsPerBlock + wave * (64 * R);
             lrow0 = w0 + R * lane;
             active = w0 < n;
-            float lane_span = 0.0f;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int i = lrow0 + r;
                 const float4 a = rq.ev32[2 * (size_t)i];
                 const float4 b = rq.ev32[2 * (size_t)i + 1];
-                if (r == 0) {
-                    t0h = a.z;
-                    t0l = b.z;
-                }
                 xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
-                const float tu = (a.z - t0h) + (b.z - t0l);
-                ti[r] = fmaf(tu, tsh, tu * tsl);
                 th[r] = a.z;
                 tl[r] = b.z;
-                if (i < n) lane_span = tu;  // rows are time-sorted: the last valid row is the latest
             }
-            span = uniform(wave_max(lane_span));
             t_first = uniform(rq.ev32[2 * (size_t)min(w0, n - 1)].z + rq.ev32[2 * (size_t)min(w0, n - 1) + 1].z);
             clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
 #pragma unroll
@@ -563,11 +546,20 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
         const int tile = ZSKIP ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
         const int j0 = tile * kTile;
         __syncthreads();
+        {
+            // Each column's scaled time since the tile's first event goes into the .w of its hi
+            // part (read by far tiles only).
+            const float c0h = rq.ev32[2 * (size_t)j0].z, c0l = rq.ev32[2 * (size_t)j0 + 1].z;
 #pragma unroll
-        for (int c = threadIdx.x; c < kTile; c += NT) {
-            const float4* src = rq.ev32 + 2 * (size_t)(j0 + c);
-            sj[2 * c] = src[0];
-            sj[2 * c + 1] = src[1];
+            for (int c = threadIdx.x; c < kTile; c += NT) {
+                const float4* src = rq.ev32 + 2 * (size_t)(j0 + c);
+                float4 hi = src[0];
+                const float4 lo = src[1];
+                const float tu = (hi.z - c0h) + (lo.z - c0l);
+                hi.w = fmaf(tu, tsh, tu * tsl);
+                sj[2 * c] = hi;
+                sj[2 * c + 1] = lo;
+            }
         }
         __syncthreads();
         int mode;
@@ -580,10 +572,15 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
             for (int qq = 0; qq < KC; ++qq)
 #pragma unroll
                 for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
-        } else if (mode == kFullLow && far_tile(sj, t_first, span)) {
-            // With the gradient the registers are short: the lane-origin row times are formed
-            // per tile instead of being kept live across tiles.
-            if (GRAD) lane_times(rq.ev32, lrow0, tsh, tsl, t0h, t0l, ti);
+        } else if (mode == kFullLow && far_tile_by_span(sj, t_first)) {
+            if (GRAD) {  // short of registers: the row times are reloaded rather than kept
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    th[r] = rq.ev32[2 * (size_t)(lrow0 + r)].z;
+                    tl[r] = rq.ev32[2 * (size_t)(lrow0 + r) + 1].z;
+                }
+            }
+            tile_times(th, tl, sj[0].z, sj[1].z, tsh, tsl, ti);
             const int ct[R] = {};  // not read: every column of the tile is causal for every row
             int far_mode = kFullLow;
             if (ZSKIP) {
@@ -593,13 +590,13 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
                 far_mode = no_b ? (no_e ? kSkip : kFullLowE) : (no_e ? kFullLowB : kFullLow);
             }
             if (far_mode == kFullLow)
-                sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, tsh, tsl,
+                sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, tsh, tsl,
                                                      nab, nae, kte, s, comp, colw, red_lds[wave], lane);
             else if (far_mode == kFullLowB)
-                sym_tile_fp32<kFullLowB, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, tsh, tsl,
+                sym_tile_fp32<kFullLowB, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, tsh, tsl,
                                                       nab, nae, kte, s, comp, colw, red_lds[wave], lane);
             else if (far_mode == kFullLowE)
-                sym_tile_fp32<kFullLowE, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, tsh, tsl,
+                sym_tile_fp32<kFullLowE, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, tsh, tsl,
                                                       nab, nae, kte, s, comp, colw, red_lds[wave], lane);
             else
 #pragma unroll
@@ -608,7 +605,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
                     for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
         } else {
             // Tiles that straddle the rows' causal counts or their own positions, and causal tiles
-            // closer in time to the rows than kNearSpans lane spans (taken by the masked path, whose
+            // closer in time to the rows than kNearTiles tile spans (taken by the masked path, whose
             // masks then pass every pair): exact time differences, from the row times loaded here.
             int ct[R];
 #pragma unroll
@@ -620,10 +617,10 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
                 }
             }
             if (mode == kDiag)
-                sym_tile_fp32<kDiag, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, tsh, tsl, nab,
+                sym_tile_fp32<kDiag, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, tsh, tsl, nab,
                                                   nae, kte, s, comp, colw, red_lds[wave], lane);
             else
-                sym_tile_fp32<kMaskLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, tsh, tsl,
+                sym_tile_fp32<kMaskLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, tsh, tsl,
                                                      nab, nae, kte, s, comp, colw, red_lds[wave], lane);
         }
         __syncthreads();
