@@ -221,3 +221,28 @@ def test_fp32c_minute_scale_triggers_over_long_window(ctx):
     t = np.concatenate([tp, tk])
     xy = np.concatenate([xp, xk])
     check_full(ctx, xy[:, 0], xy[:, 1], t, (1.0, 1.6, 14.0, 0.153, 1440.0, 0.0695), "minutes over 20,000 days")
+
+
+def test_fp32c_bursty_times(ctx):
+    """Far-tile time differences: 24 bursts of 250 events, each within 0.05 days, 0.5-3 days
+    apart, plus 500 scattered events, with tau_t = 0.5 days and 1 / omega = 6 hours.  Column tiles
+    inside a burst span minutes and tiles across a gap span days, so tiles a few of their own spans
+    before the rows (measured from the tile's first event) hold pairs that matter for both
+    kernels.  Log-likelihood, gradient and every per-event sum against the oracle."""
+    rng = np.random.default_rng(13)
+    starts = np.cumsum(rng.uniform(0.5, 3.0, 24))
+    t = np.concatenate([s + rng.uniform(0, 0.05, 250) for s in starts] + [rng.uniform(0, starts[-1], 500)])
+    centres = rng.uniform(0, 5, (24, 2))
+    xy = np.concatenate([c + rng.normal(0, 0.3, (250, 2)) for c in centres] + [rng.uniform(0, 5, (500, 2))])
+    th = (1.0, 0.5, 0.5, 0.3, 4.0, 0.1)
+    check_full(ctx, xy[:, 0], xy[:, 1], t, th, "bursty times")
+    ds = ctx.dataset(xy[:, 0], xy[:, 1], t)
+    try:
+        sums = ctx.shard_sums(ds, th, 0, 1, "fp32c")
+    finally:
+        ds.close()
+    idx = np.arange(0, t.size, 5)
+    ref = oracle.rows(xy[:, 0], xy[:, 1], t, th, idx)["sums"]
+    scale = np.maximum(np.abs(ref), np.abs(ref).max(axis=0) * 1e-12)
+    err = (np.abs(sums[idx] - ref) / scale).max(axis=0)
+    assert err.max() <= TOL["fp32c"], err
