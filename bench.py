@@ -150,6 +150,69 @@ def cpu_model():
     return None
 
 
+def gfx_clocks_ghz():
+    """Graphics clocks (GHz) that amd-smi reports now, per GPU it lists: {gpu: [one per XCD]}, or None."""
+    import re
+    import subprocess
+    try:
+        r = subprocess.run(["amd-smi", "metric", "-c", "--json"], capture_output=True, text=True, timeout=30)
+        data = json.loads(r.stdout)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        return None
+    clocks = {}
+
+    def walk(o, path):
+        if isinstance(o, dict):
+            for k, v in o.items():
+                walk(v, path + [str(k)])
+        elif isinstance(o, list):
+            for i, v in enumerate(o):
+                walk(v, path + [str(i)])
+        elif isinstance(o, (int, float)):
+            m = re.search(r"(^|/)(\d+)/clock/gfx_\d+/clk/value$", "/".join(path))
+            if m:
+                clocks.setdefault(int(m.group(2)), []).append(o / 1e3)
+
+    walk(data, [])
+    return clocks or None
+
+
+def engine_clock(ctx, ds, theta, nsamples=2):
+    """The graphics clock while the FP32C gradient runs back to back: amd-smi sampled under that
+    load, after a second of it (its reading lags a change of load by a fraction of a second); of
+    the GPUs it lists, the one with the highest mean clock (the loaded one).  None where amd-smi
+    is unavailable."""
+    import threading
+    stop = threading.Event()
+    done = [0]
+
+    def load():
+        while not stop.is_set():
+            ctx.grad(ds, theta, "fp32c")
+            done[0] += 1
+
+    worker = threading.Thread(target=load)
+    worker.start()
+    samples = []
+    try:
+        time.sleep(1.0)
+        for _ in range(nsamples):
+            c = gfx_clocks_ghz()
+            if c is None:
+                break
+            gpu = max(c, key=lambda k: sum(c[k]) / len(c[k]))
+            samples.append(c[gpu])
+            time.sleep(0.25)
+    finally:
+        stop.set()
+        worker.join()
+    if not samples:
+        return None
+    per_xcd = [sum(v) / len(v) for v in zip(*samples)]
+    return {"measured_ghz": sum(per_xcd) / len(per_xcd), "per_xcd_ghz": per_xcd, "samples": len(samples),
+            "evaluations_meanwhile": done[0]}
+
+
 def cpu_full_run():
     """One-off: the FP64 oracle over whole workloads on the host (not part of the default run):
     the 2,000-event workload, a seeded 20,000-event subsample of the 10^6-event one, and the full
@@ -543,6 +606,15 @@ def main():
                           "grad_plain_rel": (np.abs(g - g64) / np.abs(g64)).tolist()},
         "loglik": ell,
     }
+    if not args.timing_only:
+        clk = engine_clock(ctx, ds, theta)
+        if clk is not None:
+            # Both rates of R32 scale with the clock.
+            clk["spec_ghz"] = CLOCK / 1e9
+            clk["frac_at_measured_clock"] = achieved / (roof * clk["measured_ghz"] / clk["spec_ghz"])
+            clk["source"] = ("amd-smi metric -c: per-XCD graphics clocks sampled twice while the gradient "
+                             "pass ran back to back after the timed steps")
+        result["roofline"]["clock"] = clk
     ds.close()
     if not args.timing_only:
         result["posterior_regime"] = posterior_regime(ctx)

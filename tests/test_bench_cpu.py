@@ -50,3 +50,28 @@ def test_more_than_one_gpu_is_refused():
                        text=True, cwd=ROOT)
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
+
+
+def test_gfx_clock_parsing(monkeypatch):
+    """amd-smi's per-XCD graphics clocks (MHz) are read per listed GPU; other clocks are ignored,
+    and a missing or failing amd-smi gives None."""
+    import subprocess
+
+    fake = {"gpu_data": [
+        {"gpu": 0, "clock": {"gfx_0": {"clk": {"value": 2390, "unit": "MHz"}, "min_clk": {"value": 500}},
+                             "gfx_1": {"clk": {"value": 2370, "unit": "MHz"}},
+                             "mem_0": {"clk": {"value": 2000, "unit": "MHz"}}}},
+        {"gpu": 1, "clock": {"gfx_0": {"clk": {"value": 95, "unit": "MHz"}}}},
+    ]}
+
+    class Done:
+        stdout = json.dumps(fake)
+
+    monkeypatch.setattr(subprocess, "run", lambda *a, **k: Done())
+    assert bench.gfx_clocks_ghz() == {0: [2.39, 2.37], 1: [0.095]}
+
+    def missing(*a, **k):
+        raise FileNotFoundError("amd-smi")
+
+    monkeypatch.setattr(subprocess, "run", missing)
+    assert bench.gfx_clocks_ghz() is None
