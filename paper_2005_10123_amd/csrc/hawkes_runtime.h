@@ -112,7 +112,7 @@ void zero_gaps(const hawkes_params& p, int precision, double T, double& backgrou
 void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const Carved& cv, PairReq& r);
 void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool grad, int precision, const Carved& cv,
               EpiReq& e);
-Carved carve(char* base, const Plan& pl, int64_t n, bool rows);
+Carved carve(char* base, const Plan& pl, bool rows);
 hawkes_status dev_alloc(hawkes_ctx* c, void** p, size_t bytes);
 void dev_free(hawkes_ctx* c, void* p, size_t bytes);
 Dataset* find_dataset(hawkes_ctx* c, int32_t id);

@@ -288,7 +288,7 @@ void Scratch::release(hawkes_ctx* c)
 
 // Carve one evaluation's scratch: row partials, column partials, block partials, 7 result doubles,
 // zero-tile skipping tables, per-row output.
-Carved carve(char* base, const Plan& pl, int64_t n, bool rows)
+Carved carve(char* base, const Plan& pl, bool rows)
 {
     Carved cv;
     double* p = (double*)base;
@@ -311,7 +311,7 @@ hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params&
                            bool want_rows, hipStream_t s)
 {
     const Plan pl = make_plan(c, d.n, d.npad, grad, precision, c->scheme, 0, 1, c->zero_skip);
-    Carved cv = carve(scratch, pl, d.n, want_rows);
+    Carved cv = carve(scratch, pl, want_rows);
     if (out7_override) cv.out7 = out7_override;
 
     PairBatch pb;

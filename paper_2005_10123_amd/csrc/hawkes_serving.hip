@@ -222,7 +222,7 @@ void admit(hawkes_ctx* c, Server* sv)
                     continue;
                 }
                 sv->pool[bi].busy = true;
-                Carved cv = carve(sv->pool[bi].s.base, pl, d->n, false);
+                Carved cv = carve(sv->pool[bi].s.base, pl, false);
                 cv.out7 = L.d_out + 8 * nb;
                 fill_pair(p.req.p, *d, pl, cv, pb.r[nb]);
                 pb.r[nb].item_begin = items;

@@ -31,7 +31,7 @@ hawkes_status hawkes_shard_sums(hawkes_ctx* c, int32_t id, const hawkes_params* 
     hipStream_t s = c->stream;
     hipError_t e = hipStreamWaitEvent(s, c->blk_free, 0);
     if (e != hipSuccess) return poison(c, hip_fail(e, "hipStreamWaitEvent"));
-    const Carved cv = carve(c->blk.base, pl, d->n, false);
+    const Carved cv = carve(c->blk.base, pl, false);
     double* dsums = (double*)(c->blk.base + base_bytes);
 
     PairBatch pb;
