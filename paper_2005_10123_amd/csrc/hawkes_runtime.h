@@ -78,7 +78,7 @@ struct hawkes_ctx {
     hawkes::Scratch blk;       // scratch of blocking and device calls
     hipEvent_t blk_free = nullptr;  // recorded after the last use of blk
     double* h_out7 = nullptr;  // pinned
-    bool poisoned = false;
+    std::atomic<bool> poisoned{false};  // set after a device failure; read by every call, without mu
     bool profile = false;
     bool prof_pending = false;
     hipEvent_t prof_ev[2] = {nullptr, nullptr};
