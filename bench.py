@@ -524,6 +524,8 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB mebibytes (5 times), the reference "
                          "for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters, then exit")
+    ap.add_argument("--loglik-only", action="store_true",
+                    help="only the log-likelihood-only workload (both precisions), for profiler runs")
     ap.add_argument("--cpu-full", action="store_true",
                     help="only time the FP64 oracle over whole workloads on the host (minutes), then exit")
     args = ap.parse_args()
@@ -549,6 +551,13 @@ def main():
         sys.exit(2)
 
     import torch
+
+    if args.loglik_only:
+        from paper_2005_10123_amd import binding
+
+        with binding.Context(0) as ctx:
+            print(json.dumps({"loglik_workload": loglik_workload(ctx)}), flush=True)
+        return
 
     from paper_2005_10123_amd import binding, synth
 
