@@ -588,7 +588,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32c",
+        "dtype": "f32",  # pair terms in binary32 with compensated sums; epilogue and reductions in binary64
         "data": "synthetic: seeded branching (Hawkes cluster) simulation, 3-component Gaussian-mixture background",
         "config": {"workload": f"{args.workload}: N={n} events, {spec.L:g}x{spec.L:g} km, {spec.T_end:g} days; "
                                f"theta=(mu0, tau_x, tau_t, theta, omega, h)={tuple(theta)}; fused log-likelihood + "
