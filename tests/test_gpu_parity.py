@@ -246,3 +246,16 @@ def test_fp32c_bursty_times(ctx):
     scale = np.maximum(np.abs(ref), np.abs(ref).max(axis=0) * 1e-12)
     err = (np.abs(sums[idx] - ref) / scale).max(axis=0)
     assert err.max() <= TOL["fp32c"], err
+
+
+def test_large_time_offset(ctx):
+    """3,000 events in a 500-day window that starts at day 100,000 (times are centred on the data's
+    own range before the binary32 split; the integrated intensity uses the absolute times and T),
+    with tau_t = 5 days and 1 / omega = 12 hours so that time differences matter."""
+    rng = np.random.default_rng(14)
+    n = 3000
+    t = 1.0e5 + np.sort(rng.uniform(0, 500, n))
+    t[1::3] = t[0::3][: t[1::3].size] + rng.exponential(0.1, t[1::3].size)
+    xy = rng.uniform(0, 8, (n, 2))
+    xy[1::3] = xy[0::3][: xy[1::3].shape[0]] + rng.normal(0, 0.05, (xy[1::3].shape[0], 2))
+    check_full(ctx, xy[:, 0], xy[:, 1], t, (0.8, 0.4, 5.0, 0.4, 2.0, 0.06), "t from day 100,000")
