@@ -75,3 +75,32 @@ def test_gfx_clock_parsing(monkeypatch):
 
     monkeypatch.setattr(subprocess, "run", missing)
     assert bench.gfx_clocks_ghz() is None
+
+
+def test_engine_clock_samples_under_load(monkeypatch):
+    """The clock is read while evaluations run back to back (a worker thread), from the loaded GPU
+    (highest mean clock), averaged per XCD over the samples; the worker stops afterwards.  None
+    when amd-smi gives nothing."""
+    import threading
+
+    calls = []
+    running = threading.Event()
+
+    class FakeCtx:
+        def grad(self, ds, theta, precision):
+            running.set()
+            calls.append(precision)
+
+    readings = iter([{0: [2.38, 2.36], 1: [0.1, 0.1]}, {0: [2.40, 2.34], 1: [0.1, 0.1]}])
+    monkeypatch.setattr(bench.time, "sleep", lambda s: running.wait(5.0))
+    monkeypatch.setattr(bench, "gfx_clocks_ghz", lambda: next(readings))
+    clk = bench.engine_clock(FakeCtx(), None, None, nsamples=2)
+    assert clk["samples"] == 2
+    assert all(abs(a - b) < 1e-12 for a, b in zip(clk["per_xcd_ghz"], [2.39, 2.35]))
+    assert abs(clk["measured_ghz"] - 2.37) < 1e-12
+    assert clk["evaluations_meanwhile"] >= 1 and set(calls) == {"fp32c"}
+    n = len(calls)
+    threading.Event().wait(0.05)
+    assert len(calls) == n  # the worker has stopped
+    monkeypatch.setattr(bench, "gfx_clocks_ghz", lambda: None)
+    assert bench.engine_clock(FakeCtx(), None, None) is None
