@@ -4,8 +4,11 @@ Each ``pin_*`` function takes a loaded oracle library (the real one or a planted
 raises ``AssertionError`` when the oracle disagrees with an independent evaluation:
 
 * ``pin_n1``          N = 1 closed form of the log-likelihood and its gradient;
-* ``pin_library``     per-event lambda_n and Lambda_n from scipy.stats probability densities
-                      (3-D normal background kernel, exponential x 2-D normal trigger);
+* ``pin_library``     per-event lambda_n, Lambda_n and pi_n = xi_n / lambda_n from scipy.stats
+                      probability densities (3-D normal background kernel, exponential x 2-D
+                      normal trigger; xi_n the trigger part of lambda_n);
+* ``pin_rows``        the selected-rows entry point against the whole evaluation, and its six
+                      per-event sums against density ratios of scipy.stats kernels summed in numpy;
 * ``pin_mpmath``      40-digit brute-force sums of mpmath normal densities on the small fixtures,
                       with the gradient from mpmath's numerical differentiation;
 * ``pin_quadrature``  adaptive quadrature of the intensity over [0, T] against the closed-form
@@ -78,8 +81,9 @@ def pin_n1(lib):
 
 
 # ----------------------------------------------------------------------------------------------
-def library_rows(x, y, t, th):
-    """lambda_n and Lambda_n from scipy.stats densities (independent of the oracle's algebra)."""
+def library_rows(x, y, t, th, with_trigger=False):
+    """lambda_n and Lambda_n from scipy.stats densities (independent of the oracle's algebra);
+    with ``with_trigger`` also xi_n, the trigger (self-excitation) part of lambda_n."""
     from scipy.stats import expon, multivariate_normal, norm
 
     mu0, tx, tt, theta, omega, h = th
@@ -87,6 +91,7 @@ def library_rows(x, y, t, th):
     T = t.max()
     lam = np.empty(x.size)
     Lam = np.empty(x.size)
+    xi = np.zeros(x.size)
     for i in range(x.size):
         bg = multivariate_normal(mean=pts[i], cov=np.diag([tx**2, tx**2, tt**2])).pdf(pts)
         bg = np.atleast_1d(bg)
@@ -95,9 +100,12 @@ def library_rows(x, y, t, th):
         if causal.any():
             sp = multivariate_normal(mean=pts[i, :2], cov=h**2 * np.eye(2)).pdf(pts[causal, :2])
             ex = np.sum(np.atleast_1d(sp) * expon(scale=1 / omega).pdf(t[i] - t[causal]))
-        lam[i] = mu0 * bg.sum() + theta * ex
+        xi[i] = theta * ex
+        lam[i] = mu0 * bg.sum() + xi[i]
         Lam[i] = (mu0 * (norm.cdf(T, loc=t[i], scale=tt) - norm.cdf(0.0, loc=t[i], scale=tt))
                   + theta * expon(scale=1 / omega).cdf(T - t[i]))
+    if with_trigger:
+        return lam, Lam, xi
     return lam, Lam
 
 
@@ -110,11 +118,74 @@ def pin_library(lib):
             t[3] = t[4]  # a tie
         th = rng.uniform([0.3, 0.2, 1.0, 0.05, 0.2, 0.05], [2.0, 1.5, 10.0, 0.9, 3.0, 0.6])
         res = oracle.evaluate(x, y, t, th, lib=lib, rows=True)
-        lam, Lam = library_rows(x, y, t, th)
+        lam, Lam, xi = library_rows(x, y, t, th, with_trigger=True)
         ell_lib = np.log(lam) - Lam
         assert np.max(np.abs(res["row_ell"] - ell_lib) / np.abs(ell_lib)) < 1e-12, "row ell vs scipy"
         assert np.max(np.abs(res["row_Lambda"] - Lam) / np.abs(Lam)) < 1e-12, "Lambda vs scipy"
         assert _rel(res["ell"], ell_lib.sum()) < 1e-12, "ell vs scipy"
+        # Self-excitation probability (Section 2.1, probability equation): the trigger part of
+        # lambda_n over lambda_n.  Events with no causal predecessor have pi_n = 0 exactly.
+        pi_lib = xi / lam
+        assert np.all(res["row_pi"][xi == 0] == 0.0), "pi of untriggerable events"
+        pos = xi > 0
+        assert pos.sum() >= n // 2, "the case must hold triggerable events"
+        assert np.max(np.abs(res["row_pi"][pos] - pi_lib[pos]) / pi_lib[pos]) < 1e-12, "pi vs scipy"
+
+
+# ----------------------------------------------------------------------------------------------
+def library_sums(x, y, t, th):
+    """The six per-event sums S_b, S_br, S_bt, S_e, S_et, S_er of the unnormalised kernels, each
+    kernel value taken as a scipy.stats density divided by the same density at its own mean (so no
+    normalising constant is retyped here): B_ij = N3(p_j; p_i, diag(tx^2, tx^2, tt^2)) / peak and,
+    for t_j < t_i, E_ij = Exp(t_i - t_j; omega) N2(x_j; x_i, h^2 I) / (Exp(0; omega) N2 peak).
+    The moments weight them by r^2 = |x_i - x_j|^2 and dt = t_i - t_j (dt^2 for the background)."""
+    from scipy.stats import expon, multivariate_normal
+
+    _, tx, tt, _, omega, h = th
+    pts = np.stack([x, y, t], axis=1)
+    out = np.zeros((x.size, 6))
+    for i in range(x.size):
+        bmv = multivariate_normal(mean=pts[i], cov=np.diag([tx**2, tx**2, tt**2]))
+        B = np.atleast_1d(bmv.pdf(pts)) / bmv.pdf(pts[i])
+        r2 = (x[i] - x) ** 2 + (y[i] - y) ** 2
+        dt = t[i] - t
+        out[i, 0] = B.sum()
+        out[i, 1] = (r2 * B).sum()
+        out[i, 2] = (dt * dt * B).sum()
+        causal = t < t[i]
+        if causal.any():
+            smv = multivariate_normal(mean=pts[i, :2], cov=h**2 * np.eye(2))
+            ex = expon(scale=1 / omega)
+            E = (np.atleast_1d(smv.pdf(pts[causal, :2])) * ex.pdf(dt[causal])) / (smv.pdf(pts[i, :2]) * ex.pdf(0.0))
+            out[i, 3] = E.sum()
+            out[i, 4] = (dt[causal] * E).sum()
+            out[i, 5] = (r2[causal] * E).sum()
+    return out
+
+
+def pin_rows(lib):
+    """``hawkes_oracle_rows`` (16 doubles per selected event) against the whole evaluation and
+    against the library densities: every field in its documented slot, for rows in any order."""
+    rng = np.random.default_rng(21)
+    x, y, t = random_events(30, 2100, L=0.8, T=6.0)
+    t[7] = t[8]  # a tie
+    th = np.array([1.1, 0.45, 1.5, 0.6, 0.9, 0.3])
+    full = oracle.evaluate(x, y, t, th, lib=lib, rows=True)
+    idx = rng.permutation(x.size)[:23]
+    r = oracle.rows(x, y, t, th, idx, lib=lib)
+    assert np.array_equal(r["ell"], full["row_ell"][idx]), "rows: ell slot"
+    assert np.array_equal(r["Lambda"], full["row_Lambda"][idx]), "rows: Lambda slot"
+    assert np.array_equal(r["pi"], full["row_pi"][idx]), "rows: pi slot"
+    assert np.array_equal(r["grad"], full["row_grad"][idx]), "rows: gradient slots"
+    lam_lib, Lam_lib, xi_lib = library_rows(x, y, t, th, with_trigger=True)
+    assert np.max(np.abs(r["lambda"] - lam_lib[idx]) / lam_lib[idx]) < 1e-12, "rows: lambda slot"
+    sums = library_sums(x, y, t, th)[idx]
+    assert np.all(sums[:, 3:] > 0) or np.any(xi_lib[idx] == 0), "the case must exercise the trigger sums"
+    scale = np.maximum(np.abs(sums), 1e-300)
+    nz = np.abs(sums) > 0
+    assert np.all(r["sums"][~nz] == 0.0), "rows: sums of events without causal predecessors"
+    err = np.abs(r["sums"] - sums) / scale
+    assert np.max(err[nz]) < 1e-12, ("rows: sums vs scipy", err.max(axis=0))
 
 
 # ----------------------------------------------------------------------------------------------
@@ -260,4 +331,4 @@ def pin_invariants(lib):
     assert pi[np.argmin(t)] == 0.0, "the earliest event cannot be triggered"
 
 
-ALL_PINS = [pin_n1, pin_library, pin_mpmath, pin_quadrature, pin_fd, pin_identity, pin_invariants]
+ALL_PINS = [pin_n1, pin_library, pin_rows, pin_mpmath, pin_quadrature, pin_fd, pin_identity, pin_invariants]

@@ -49,6 +49,17 @@ MUTANTS = [
     ("pi from the background part", "out->pi = ce * Se / lambda;", "out->pi = cb * Sb / lambda;"),
     ("Sbr weighted by dt", "Sbr += r2 * b;", "Sbr += dt * b;"),
     ("Set weighted by r2", "Set += dt * e;", "Set += r2 * e;"),
+    ("Ser weighted by dt", "Ser += r2 * e;", "Ser += dt * e;"),
+    ("pi without the trigger coefficient", "out->pi = ce * Se / lambda;", "out->pi = Se / lambda;"),
+    ("pi over the background part of lambda", "out->pi = ce * Se / lambda;", "out->pi = ce * Se / (cb * Sb);"),
+    ("two per-event sums swapped", "out->sums[1] = Sbr;\n    out->sums[2] = Sbt;",
+     "out->sums[1] = Sbt;\n    out->sums[2] = Sbr;"),
+    ("trigger sums written in the wrong order", "out->sums[4] = Set;\n    out->sums[5] = Ser;",
+     "out->sums[4] = Ser;\n    out->sums[5] = Set;"),
+    ("row layout: lambda and Lambda swapped", "o[0] = r.lambda;\n        o[1] = r.Lambda;",
+     "o[0] = r.Lambda;\n        o[1] = r.lambda;"),
+    ("row layout: ell and pi swapped", "o[2] = r.ell;\n        o[3] = r.pi;", "o[2] = r.pi;\n        o[3] = r.ell;"),
+    ("row layout: sums one slot early", "o[10 + p] = r.sums[p];", "o[9 + p] = r.sums[p];"),
 ]
 
 
