@@ -70,3 +70,16 @@ def test_failures_are_logged_when_asked(tmp_path):
     env["HAWKES_LOG"] = "0"
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
     assert "libhawkes" not in r.stderr
+
+
+def test_package_star_import_names_real_modules():
+    """Every name the package lists in __all__ is a module of the package."""
+    import importlib
+
+    import paper_2005_10123_amd as pkg
+
+    for name in pkg.__all__:
+        importlib.import_module(f"paper_2005_10123_amd.{name}")
+    ns = {}
+    exec("from paper_2005_10123_amd import *", ns)
+    assert set(pkg.__all__) <= set(ns)
