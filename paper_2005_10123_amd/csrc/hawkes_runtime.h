@@ -41,9 +41,10 @@ struct Plan {
     int ubase = 0, urem = 0;  // symmetric: block b walks ubase + (b < urem) work units
     long long units = 0;      // symmetric: (row block, column tile) units this evaluation walks
     long long ubegin = 0;     // symmetric: first of them in the row-major order of the lower triangle
-    long long col_stride = 0; // symmetric: doubles per column-sum quantity
+    long long col_stride = 0; // symmetric: values per column-sum quantity
     size_t part_doubles = 0;  // row partial sums
-    size_t col_doubles = 0;   // symmetric: column partial sums
+    size_t col_bytes = 0;     // symmetric: column partial sums (binary32 values for FP32C, binary64
+                              // for FP64), rounded up to a multiple of 8 bytes
     bool zskip = false;       // symmetric: zero-tile skipping (tables zcum, zskip in the scratch)
     bool zdirect = false;     // direct: zero-tile skipping (each row block walks its window only)
     size_t zbytes = 0;        // bytes of those tables

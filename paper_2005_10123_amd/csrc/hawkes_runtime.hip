@@ -75,7 +75,10 @@ Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precisio
         pl.urem = pl.items > 0 ? (int)(pl.units % pl.items) : 0;
         pl.part_doubles = (size_t)(pl.items + T) * pl.K * kRowsPerBlock;
         pl.col_stride = (long long)kRowsPerBlock * T * (T + 1) / 2;
-        pl.col_doubles = (size_t)(grad ? 3 : 1) * pl.col_stride;
+        // The FP32C pass writes binary32 column partials (sums of binary32 terms over one row
+        // block), the FP64 pass binary64 ones.
+        const size_t col_elem = precision == kFP32C ? sizeof(float) : sizeof(double);
+        pl.col_bytes = ((size_t)(grad ? 3 : 1) * pl.col_stride * col_elem + 7) & ~(size_t)7;
         if (zero_skip && shard == 0 && nshards == 1) {
             // Leaving tiles out only shortens the walk: the grid and the partial-sum slots stay
             // those of the whole triangle.
@@ -100,7 +103,7 @@ Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precisio
 
 size_t scratch_bytes(const Plan& pl, int64_t n, bool rows)
 {
-    size_t b = (pl.part_doubles + pl.col_doubles) * sizeof(double) + (size_t)pl.epi_blocks * 7 * sizeof(double) +
+    size_t b = pl.part_doubles * sizeof(double) + pl.col_bytes + (size_t)pl.epi_blocks * 7 * sizeof(double) +
                8 * sizeof(double) + pl.zbytes;
     if (rows) b += (size_t)n * kRowOut * sizeof(double);
     return b;
@@ -254,7 +257,7 @@ hawkes_status reserve_blocking(hawkes_ctx* c, size_t need)
     }
     if (st == HAWKES_ENOMEM && c->scheme == kSymmetric)
         // The symmetric enumeration's column partial sums grow as N^2 / 2048 values per quantity
-        // (about 5.9 GB for the FP32C gradient at N = 10^6); the direct one needs O(N).
+        // (about 5.9 GB for the FP32C gradient at N = 10^6, binary32); the direct one needs O(N).
         g_last_error += " (the symmetric pair enumeration's scratch grows as N^2; "
                         "hawkes_set_pair_scheme(ctx, HAWKES_PAIRS_DIRECT) needs memory linear in N)";
     return st;
@@ -294,8 +297,8 @@ Carved carve(char* base, const Plan& pl, bool rows)
     double* p = (double*)base;
     cv.part = p;
     p += pl.part_doubles;
-    cv.colpart = pl.col_doubles ? p : nullptr;
-    p += pl.col_doubles;
+    cv.colpart = pl.col_bytes ? p : nullptr;
+    p += pl.col_bytes / sizeof(double);
     cv.block_part = p;
     p += (size_t)pl.epi_blocks * 7;
     cv.out7 = p;

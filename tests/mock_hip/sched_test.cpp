@@ -7,6 +7,8 @@
 // result can be matched to its own request.
 #include <hawkes.h>
 
+#include "hawkes_runtime.h"
+
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -207,6 +209,61 @@ void tiny_budget_queues()
     check(hawkes_destroy(c) == HAWKES_OK, "destroy");
 }
 
+// The FP32C symmetric pass writes binary32 column partials, the FP64 one binary64: an evaluation's
+// scratch holds 4 (FP32C) or 8 (FP64) bytes per column value, carved in that order, and a budget
+// sized for k FP32C gradient requests admits k of them at once.
+void column_scratch_by_precision()
+{
+    hawkes_ctx* c = nullptr;
+    check(hawkes_create(0, 0, nullptr, &c) == HAWKES_OK, "create");
+    const int64_t n = 50000;
+    const int npad = (int)((n + hawkes::kPad - 1) / hawkes::kPad * hawkes::kPad);
+    const long long T = npad / hawkes::kRowsPerBlock;
+    const long long stride = (long long)hawkes::kRowsPerBlock * T * (T + 1) / 2;
+    for (int prec = 0; prec < 2; ++prec)
+        for (int grad = 0; grad < 2; ++grad) {
+            const hawkes::Plan pl = hawkes::make_plan(c, n, npad, grad != 0, prec, hawkes::kSymmetric);
+            const size_t elem = prec == HAWKES_FP32C ? sizeof(float) : sizeof(double);
+            const size_t col = ((size_t)(grad ? 3 : 1) * stride * elem + 7) / 8 * 8;
+            check(pl.col_stride == stride, "values per column-sum quantity");
+            check(pl.col_bytes == col, "column partials sized by the pass's element type");
+            const size_t want = pl.part_doubles * sizeof(double) + col + (size_t)pl.epi_blocks * 7 * sizeof(double) +
+                                8 * sizeof(double);
+            check(hawkes::scratch_bytes(pl, n, false) == want, "scratch bytes of one evaluation");
+            std::vector<char> buf(want);
+            const hawkes::Carved cv = hawkes::carve(buf.data(), pl, false);
+            check((char*)cv.colpart - buf.data() == (ptrdiff_t)(pl.part_doubles * sizeof(double)), "column partials carved after the row partials");
+            check((char*)cv.block_part - (char*)cv.colpart == (ptrdiff_t)col, "block partials carved after the column partials");
+            check((char*)(cv.out7 + 8) - buf.data() == (ptrdiff_t)want, "the carve fills the scratch exactly");
+        }
+    // Budget admission: room for the dataset and four FP32C gradient requests (the pool rounds
+    // each buffer up to a MiB), not five.
+    const hawkes::Plan pl = hawkes::make_plan(c, n, npad, true, HAWKES_FP32C, hawkes::kSymmetric);
+    check(hawkes_destroy(c) == HAWKES_OK, "destroy");
+    const size_t mib = (size_t)1 << 20;
+    const size_t per = (hawkes::scratch_bytes(pl, n, false) + mib - 1) / mib * mib;
+    hawkes_ctx* probe = nullptr;
+    check(hawkes_create(0, 0, nullptr, &probe) == HAWKES_OK, "create probe");
+    size_t ds_bytes = 0;
+    int64_t nn = 0;
+    check(hawkes_dataset_info(probe, make_dataset(probe, n, 16), &nn, &ds_bytes) == HAWKES_OK, "dataset_info");
+    check(hawkes_destroy(probe) == HAWKES_OK, "destroy probe");
+    mock_set_latency_us(3000);
+    check(hawkes_create(0, ds_bytes + 4 * per + per / 2, nullptr, &c) == HAWKES_OK, "create");
+    const int32_t d = make_dataset(c, n, 16);
+    const long long base = mock_device_bytes();
+    mock_reset_peak();
+    std::vector<hawkes_request> reqs;
+    for (uint64_t tag = 0; tag < 24; ++tag) reqs.push_back(request(d, HAWKES_FP32C, 1, 1e-3 * tag, tag));
+    check(hawkes_submit(c, reqs.data(), (int32_t)reqs.size()) == HAWKES_OK, "submit");
+    const auto got = collect(c, reqs.size());
+    mock_set_latency_us(200);
+    check(got.size() == reqs.size(), "every request completes");
+    for (const auto& r : got) check(matches(r, reqs[r.tag], n), "result");
+    check(mock_peak_device_bytes() - base == (long long)(4 * per), "four FP32C requests' scratch at once");
+    check(hawkes_destroy(c) == HAWKES_OK, "destroy");
+}
+
 void too_large_fails_alone()
 {
     hawkes_ctx* probe = nullptr;
@@ -361,6 +418,7 @@ int main()
     run("basic_mix", basic_mix);
     run("blocking_beside_serving", blocking_beside_serving);
     run("tiny_budget_queues", tiny_budget_queues);
+    run("column_scratch_by_precision", column_scratch_by_precision);
     run("too_large_fails_alone", too_large_fails_alone);
     run("invalid_requests_fail_alone", invalid_requests_fail_alone);
     run("busy_dataset", busy_dataset);

@@ -1,5 +1,7 @@
 """The host runtime and the request scheduler of libhawkes, built for the CPU against a test double
 of the device (tests/mock_hip): admission under a tiny HBM budget (requests queue rather than fail),
+the size and carving of one evaluation's scratch by precision (binary32 column partials for FP32C)
+with a budget for four FP32C requests admitting four at once,
 a request that can never fit failing alone, invalid requests failing alone, a busy dataset, eight
 threads submitting and polling at once, a device failure that fails its requests and makes the
 context unusable, and teardown with requests pending and in flight (tests/mock_hip/sched_test.cpp).
@@ -17,7 +19,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2005_10123_amd", "csrc")
 MOCK = os.path.join(ROOT, "tests", "mock_hip")
 CLANG = "/opt/rocm/llvm/bin/clang++"
-SCENARIOS = ["basic_mix", "blocking_beside_serving", "tiny_budget_queues", "too_large_fails_alone",
+SCENARIOS = ["basic_mix", "blocking_beside_serving", "tiny_budget_queues", "column_scratch_by_precision",
+             "too_large_fails_alone",
              "invalid_requests_fail_alone", "busy_dataset", "many_threads", "device_failure_poisons",
              "destroy_in_flight"]
 BUILDS = {
