@@ -9,6 +9,7 @@ compiles it with gcc and marshals numpy arrays through ctypes.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 
@@ -111,3 +112,26 @@ def rows(x, y, t, theta, row_index, lib=None):
         raise ValueError("oracle rejected its input")
     return {"lambda": out[:, 0].copy(), "Lambda": out[:, 1].copy(), "ell": out[:, 2].copy(),
             "pi": out[:, 3].copy(), "grad": out[:, 4:10].copy(), "sums": out[:, 10:16].copy()}
+
+
+def evaluate_parallel(x, y, t, theta, threads: int | None = None, lib=None):
+    """The whole evaluation (``evaluate(..., rows=True)``) with the rows split into contiguous
+    ranges run on host threads (the C loop releases the interpreter lock): each range goes
+    through ``hawkes_oracle_rows``, which evaluates every row exactly as ``evaluate`` does.  The
+    totals are the exactly rounded sums (``math.fsum``) of the per-event values, so they do not
+    depend on the split.  Returns the same dict as ``evaluate(rows=True)`` plus ``row_lambda``
+    and ``row_sums`` (n x 6)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    lib = lib or load()
+    x, y, t = _events(x, y, t)
+    n = x.size
+    if threads is None:
+        threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    parts = [p for p in np.array_split(np.arange(n, dtype=np.int64), threads) if p.size]
+    with ThreadPoolExecutor(len(parts)) as pool:
+        res = list(pool.map(lambda idx: rows(x, y, t, theta, idx, lib=lib), parts))
+    cat = {k: np.concatenate([r[k] for r in res]) for k in res[0]}
+    return {"ell": math.fsum(cat["ell"]), "grad": np.array([math.fsum(cat["grad"][:, p]) for p in range(6)]),
+            "row_ell": cat["ell"], "row_Lambda": cat["Lambda"], "row_pi": cat["pi"], "row_grad": cat["grad"],
+            "row_lambda": cat["lambda"], "row_sums": cat["sums"]}

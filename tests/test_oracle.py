@@ -80,3 +80,19 @@ def test_pins_catch_planted_mistake(tmp_path, desc, old, new):
             caught.append((pin.__name__, str(exc)[:80]))
             break
     assert caught, f"no pin catches: {desc}"
+
+
+def test_parallel_driver_matches_whole_evaluation(lib):
+    """The threaded whole-workload driver (row ranges through hawkes_oracle_rows, totals by exact
+    summation) reproduces evaluate(rows=True) row by row and in total."""
+    import numpy as np
+
+    x, y, t = P.random_events(300, 77, L=2.0, T=50.0)
+    th = [1.0, 0.4, 6.0, 0.5, 0.8, 0.15]
+    whole = oracle.evaluate(x, y, t, th, lib=lib, rows=True)
+    for threads in (1, 3, 7):
+        par = oracle.evaluate_parallel(x, y, t, th, threads=threads, lib=lib)
+        for k in ("row_ell", "row_Lambda", "row_pi", "row_grad"):
+            assert np.array_equal(par[k], whole[k]), (threads, k)
+        assert abs(par["ell"] - whole["ell"]) <= 1e-13 * np.abs(whole["row_ell"]).sum()
+        assert np.all(np.abs(par["grad"] - whole["grad"]) <= 1e-13 * np.abs(whole["row_grad"]).sum(axis=0))
