@@ -1,6 +1,7 @@
 """HIP path (through the C ABI) against the FP64 oracle: small fixtures, ragged sizes spanning
-several tiles, ties and degenerate inputs, per-event outputs, the 2,000-event workload in full and
-the 85,000-event workloads on sampled rows plus size-independent properties."""
+several tiles, ties and degenerate inputs, per-event outputs, the 2,000-event workload in full, the
+85,000-event workloads in full against the oracle's whole evaluation (run on the host's threads),
+and on sampled rows plus size-independent properties."""
 import numpy as np
 import pytest
 
@@ -159,6 +160,35 @@ def test_city_fp32c_vs_fp64(ctx, city):
     assert rel(e32, e64) <= TOL["fp32c"]
     plain, normed = grad_errors(g32, g64, rows64["grad"], e64, th)
     assert np.all(normed <= TOL["fp32c"]), normed
+    assert np.all(plain <= TOL["fp32c"]), plain
+
+
+@pytest.fixture(scope="module")
+def city_oracle(city):
+    """The oracle's whole evaluation of the 85,000-event gradient workload (row ranges on the
+    host's threads; about 13 s on 16)."""
+    x, y, t, th, _ = city
+    return oracle.evaluate_parallel(x, y, t, th)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+def test_city_full_against_oracle(ctx, city, city_oracle, scheme):
+    """The headline workload in full: log-likelihood and every gradient component of both
+    precisions against the oracle's whole evaluation (plain and l1-normalised metrics), and every
+    per-event log-likelihood term and self-excitation probability."""
+    x, y, t, th, ds = city
+    ref = city_oracle
+    ctx.set_pair_scheme(scheme)
+    try:
+        for prec in PRECS:
+            ell, g = ctx.grad(ds, th, prec)
+            assert_close(ell, g, ref, prec, ("city_85k_10km, all events", scheme), th)
+            r = ctx.rows(ds, th, prec)
+            assert row_ell_error(r["ell"], ref["row_ell"]) <= TOL[prec], (scheme, prec)
+            assert np.max(np.abs(r["lambda"] - ref["row_lambda"]) / ref["row_lambda"]) <= TOL[prec], (scheme, prec)
+            assert np.max(np.abs(r["pi"] - ref["row_pi"])) <= TOL[prec], (scheme, prec)
+    finally:
+        ctx.set_pair_scheme("symmetric")
 
 
 def test_city_finite_differences(ctx, city):
@@ -192,6 +222,10 @@ def test_loglik_workload_sampled(ctx):
     e64 = ctx.loglik(ds, th, "fp64")
     e32 = ctx.loglik(ds, th, "fp32c")
     assert rel(e32, e64) <= TOL["fp32c"]
+    # Both precisions against the oracle's whole evaluation of all 85,000 events.
+    ref = oracle.evaluate_parallel(x, y, t, th)
+    assert rel(e64, ref["ell"]) <= TOL["fp64"], (e64, ref["ell"])
+    assert rel(e32, ref["ell"]) <= TOL["fp32c"], (e32, ref["ell"])
     ds.close()
 
 

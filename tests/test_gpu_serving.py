@@ -1,21 +1,26 @@
-"""Batched serving through hawkes_submit / hawkes_poll: each result equals the blocking evaluation
-alone (bitwise: same plan, same arithmetic) whatever it is batched with; invalid requests fail
+"""Batched serving through hawkes_submit / hawkes_poll: each result matches the FP64 oracle and
+equals the blocking evaluation alone (bitwise: same plan, same arithmetic) whatever it is batched
+with; invalid requests fail
 alone; a small HBM budget queues work instead of failing; destroying a busy dataset is refused;
 destroying the context with requests in flight is clean; several threads may submit at once."""
 import numpy as np
 import pytest
 
+import oracle
+from gpu_util import TOL, assert_close, rel
 from paper_2005_10123_amd import binding, synth
 
 pytestmark = pytest.mark.gpu
 
 
-def datasets(ctx, sizes, seed0=40):
-    out = []
+def datasets(ctx, sizes, seed0=40, events=False):
+    out, evs = [], []
     for k, n in enumerate(sizes):
         spec = synth.SimSpec(n, 10.0, 1000.0, 3, 0.5, 0.1, 0.3, (10123, seed0, k))
-        out.append(ctx.dataset(*synth.simulate(spec)))
-    return out
+        ev = synth.simulate(spec)
+        evs.append(ev)
+        out.append(ctx.dataset(*ev))
+    return (out, evs) if events else out
 
 
 def drain(ctx, count, timeout_s=60.0):
@@ -31,8 +36,11 @@ def drain(ctx, count, timeout_s=60.0):
 
 
 def test_alone_equals_mix():
+    """48 requests over four datasets, both precisions, with and without the gradient, submitted in
+    bursts so that launches hold several requests: every served result against the oracle's
+    evaluation of its own dataset and parameters, and bitwise equal to the blocking call."""
     ctx = binding.Context(0)
-    dss = datasets(ctx, [3000, 700, 9000, 1500])
+    dss, evs = datasets(ctx, [3000, 700, 9000, 1500], events=True)
     rng = np.random.default_rng(1)
     theta0 = np.array(synth.THETA_CFG1)
     reqs = []
@@ -45,10 +53,16 @@ def test_alone_equals_mix():
     ctx.submit(reqs[5:20])
     ctx.submit(reqs[20:])
     got = drain(ctx, len(reqs))
-    for r in reqs:
+    for k, r in enumerate(reqs):
         res = got[r.tag]
         assert res.status == 0
         prec = "fp64" if r.precision == binding.FP64 else "fp32c"
+        th = [getattr(r.p, name) for name in binding.PARAM_NAMES]
+        ref = oracle.evaluate_parallel(*evs[k % 4], th)
+        if r.want_grad:
+            assert_close(res.loglik, np.array(res.grad[:]), ref, prec, ("served", r.tag), th)
+        else:
+            assert rel(res.loglik, ref["ell"]) <= TOL[prec], (r.tag, prec, res.loglik, ref["ell"])
         if r.want_grad:
             ell, g = ctx.grad(r.dataset, r.p, prec)
             assert res.loglik == ell and np.array_equal(np.array(res.grad[:]), g), r.tag

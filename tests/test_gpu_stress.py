@@ -39,8 +39,9 @@ def test_full_size_fp32c_against_fp64(stress):
     r64 = ctx.rows(ds, th, "fp64")
     assert rel(e32, e64) <= TOL["fp32c"], (e32, e64)
     assert abs(e64 - r64["ell"].sum()) <= 1e-9 * np.abs(r64["ell"]).sum()
-    _, normed = grad_errors(g32, g64, r64["grad"], e64, th)
+    plain, normed = grad_errors(g32, g64, r64["grad"], e64, th)
     assert np.all(normed <= TOL["fp32c"]), normed
+    assert np.all(plain <= TOL["fp32c"]), plain
     # mu0 dl/dmu0 + theta dl/dtheta = N - Lambda holds at any size
     lhs = th[0] * g64[0] + th[3] * g64[3]
     assert abs(lhs - (x.size - r64["Lambda"].sum())) <= 1e-9 * x.size
