@@ -1,4 +1,6 @@
-"""Compile the HIP sources under csrc/ into the in-tree shared library libhawkes.so (gfx950).
+"""Compile the HIP sources under csrc/ into the in-tree shared library libhawkes.so (gfx950), and
+the instruction-rate microbenchmark csrc/rates_probe.hip into the executable rates_probe (the
+measured rates behind the pairwise pass's roofline; not part of the library).
 
 Run as ``python -m paper_2005_10123_amd.build`` or through ``__graft_entry__.build()``.
 """
@@ -13,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBRARY = os.path.join(HERE, "libhawkes.so")
+RATES_PROBE = os.path.join(HERE, "rates_probe")
 SOURCES = ["hawkes_kernels.hip", "hawkes_runtime.hip", "hawkes_serving.hip", "hawkes_multi.hip", "hawkes_shard.hip", "hawkes_epilogue.hip"]
 ARCH = "gfx950"
 # Packed FP32 VALU forms are switched off for all device code on this target.
@@ -39,8 +42,17 @@ def build(output: str = LIBRARY, extra_flags=()) -> str:
         _run(["hipcc", *FLAGS, *extra_flags, "-c", os.path.join(CSRC, src), "-o", obj])
         return obj
 
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    def probe():
+        if output != LIBRARY:
+            return
+        tmp_exe = RATES_PROBE + ".tmp"
+        _run(["hipcc", *FLAGS, *extra_flags, os.path.join(CSRC, "rates_probe.hip"), "-o", tmp_exe])
+        os.replace(tmp_exe, RATES_PROBE)
+
+    with ThreadPoolExecutor(max_workers=len(SOURCES) + 1) as ex:
+        probe_job = ex.submit(probe)
         objs = list(ex.map(compile_one, SOURCES))
+        probe_job.result()
     tmp = output + ".tmp"
     _run(["hipcc", "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp, "-lpthread"])
     os.replace(tmp, output)
