@@ -26,11 +26,13 @@ sys.path.insert(0, ROOT)
 # are causal): 13.5 FP32 lane operations (FMA = 1) and 1.5 exponentials for log-likelihood +
 # gradient; 10.5 and 1.5 for the log-likelihood alone.
 WORK = {True: (13.5, 1.5), False: (10.5, 1.5)}
-# The symmetric enumeration evaluates each unordered pair once: 3 differences, 2 for r^2, 1 for
-# dt^2, 1 background and 2 trigger exponent arguments, the background term and its two moments
-# added to both events (6) and the trigger term and its two moments to the later one (3), i.e.
-# 18 lane operations and 2 exponentials per unordered pair = 9 and 1 per ordered pair.
-WORK_SYM = (9.0, 1.0)
+# The symmetric enumeration (the default pass) evaluates each unordered pair once: 3 differences,
+# 2 for r^2, 1 for dt^2, 1 background and 2 trigger exponent arguments, the background term and its
+# two moments added to both events (6) and the trigger term and its two moments to the later one
+# (3), i.e. 18 lane operations and 2 exponentials per unordered pair = 9 and 1 per ordered pair.
+# Without the gradient: 7 + 2 + 1 + 1 + 2 (background term to both events) + 2 + 1 = 16 and 2 per
+# unordered pair = 8 and 1 per ordered pair.
+WORK_SYM = {True: (9.0, 1.0), False: (8.0, 1.0)}
 CUS, CLOCK = 256, 2.4e9
 P_OPS32 = 157.3e12 / 2          # FP32 vector: 157.3 TFLOP/s with FMA = 2 FLOP
 P_OPS64 = 78.6e12 / 2           # FP64 vector
@@ -69,11 +71,27 @@ def measured_traffic(record: str):
     return rec["fetch_bytes"] + rec["write_bytes"]
 
 
-def roofline_pairs(grad: bool, fp64: bool = False) -> float:
-    ops, exps = WORK[grad]
+def roofline_pairs(grad: bool, fp64: bool = False, executed: bool = False) -> float:
+    """Ordered pairs per second at the chip's peak rates for the method's work per ordered pair
+    (the direct enumeration's), or with ``executed`` for the work the symmetric pass executes."""
+    ops, exps = WORK_SYM[grad] if executed else WORK[grad]
     if fp64:
         return 1.0 / ((ops + exps * FP64_EXP_OPS) / P_OPS64)
     return 1.0 / (ops / P_OPS32 + exps / P_EXP32)
+
+
+def oracle_errors(ell, g, ref, theta):
+    """Errors of one GPU result against the oracle's whole evaluation: relative error of ell and,
+    per gradient component, the plain relative error, the error over the l1 norm of the per-event
+    terms (sum_i |g_i,p|) and the cancellation factor kappa_p = sum_i |g_i,p| / |g_p|."""
+    out = {"ell_rel": abs(ell - ref["ell"]) / abs(ref["ell"])}
+    if g is not None:
+        g = np.asarray(g, float)
+        l1 = np.abs(ref["row_grad"]).sum(axis=0)
+        out["grad_plain_rel"] = (np.abs(g - ref["grad"]) / np.maximum(np.abs(ref["grad"]), 1e-300)).tolist()
+        out["grad_l1_normalised"] = (np.abs(g - ref["grad"]) / np.maximum(l1, 1e-300)).tolist()
+        out["kappa"] = (l1 / np.maximum(np.abs(ref["grad"]), 1e-300)).tolist()
+    return out
 
 
 def time_steps(ctx, ds, theta, precision, grad, steps, warmup):
@@ -118,24 +136,20 @@ def cpu_baseline(x, y, t, theta, budget_s=12.0):
             "per_row_s": sec / m}
 
 
-def cpu_baseline_threads(x, y, t, theta, per_row_s, budget_s=8.0):
-    """The same FP64 oracle run over disjoint row partitions on the host's cores (one thread each)."""
-    from concurrent.futures import ThreadPoolExecutor
-
+def cpu_all_cores_run(x, y, t, theta):
+    """The same FP64 oracle over the whole workload, its rows split into contiguous ranges run on
+    the host's cores (one thread each, at most 16): the multi-core host context, and the oracle's
+    whole result that every GPU result of this workload is compared with."""
     import oracle
 
     threads = max(1, min(16, len(os.sched_getaffinity(0))))
     n = x.size
-    m = int(max(threads, min(n, threads * budget_s / max(per_row_s, 1e-9))))
-    idx = np.linspace(0, n - 1, m).astype(np.int64)
-    parts = np.array_split(idx, threads)
-    with ThreadPoolExecutor(threads) as pool:
-        a = time.perf_counter()
-        list(pool.map(lambda r: oracle.rows(x, y, t, theta, r), parts))
-        sec = time.perf_counter() - a
-    return {"value": m * n / sec, "unit": "pairs/s", "cores": threads, "kind": "oracle",
-            "sample": f"{m} evenly spaced rows of the {n}-event workload against all {n} events, split into "
-                      f"{threads} contiguous row ranges run concurrently; {sec:.1f} s"}
+    a = time.perf_counter()
+    ref = oracle.evaluate_parallel(x, y, t, theta, threads=threads)
+    sec = time.perf_counter() - a
+    return {"value": float(n) * n / sec, "unit": "pairs/s", "cores": threads, "kind": "oracle", "seconds": sec,
+            "sample": f"all {n} events of the workload against all {n}, split into {threads} contiguous row "
+                      f"ranges run concurrently"}, ref
 
 
 def cpu_model():
@@ -293,12 +307,64 @@ def loglik_workload(ctx, steps=10):
     ell = {}
     for prec in ("fp32c", "fp64"):
         ell[prec], wall, _, kms = time_steps(ctx, ds, theta, prec, False, steps, 2)
+        achieved = float(n) * n / (kms * 1e-3)
         out[prec] = {"ms_per_call": wall / steps * 1e3, "kernel_ms": kms, "pairs_per_s": float(n) * n * steps / wall,
-                     # the pairwise kernel against the log-likelihood roofline of the method's work
-                     "roofline_frac": float(n) * n / (kms * 1e-3) / roofline_pairs(False, prec == "fp64")}
+                     # the pairwise kernel against the roofline of the work it executes
+                     "roofline_frac": achieved / roofline_pairs(False, prec == "fp64", executed=True)}
+        if prec == "fp32c":
+            # and against the roofline of the method's work (the direct enumeration's)
+            out[prec]["method_work_frac"] = achieved / roofline_pairs(False)
     ds.close()
     out["ell_rel_fp32c_vs_fp64"] = abs(ell["fp32c"] - ell["fp64"]) / abs(ell["fp64"])
+    out["ell"] = ell
+    out["events"] = (x, y, t)
     return out
+
+
+def small_workload(ctx, steps=20):
+    """The 2,000-event workload (10 x 10 km, 1,000 days): one log-likelihood per call, FP64 (its
+    stated precision) and FP32C beside it, call and pairwise-kernel times.  The oracle's whole
+    evaluation of it is compared with both in the CPU leg."""
+    from paper_2005_10123_amd import synth
+
+    (x, y, t), theta = synth.config_events("small_2k")
+    n = x.size
+    ds = ctx.dataset(x, y, t)
+    out = {"workload": "small_2k", "n_events": n, "theta": list(theta)}
+    for prec in ("fp64", "fp32c"):
+        ell, wall, _, kms = time_steps(ctx, ds, theta, prec, False, steps, 3)
+        out[prec] = {"ms_per_call": wall / steps * 1e3, "kernel_ms": kms, "pairs_per_s": float(n) * n * steps / wall,
+                     "ell": ell}
+    ds.close()
+    return out, (x, y, t, theta)
+
+
+def stress_workload(ctx):
+    """The 1,000,000-event workload (40 x 40 km, 20,000 days): FP32C and FP64 log-likelihood +
+    gradient at full size, compared with each other, and a seeded 20,000-event subsample evaluated
+    as its own dataset by both precisions (compared with the oracle in the CPU leg)."""
+    from paper_2005_10123_amd import synth
+
+    (x, y, t), theta = synth.config_events("stress_1m")
+    n = x.size
+    ds = ctx.dataset(x, y, t)
+    out = {"workload": "stress_1m", "n_events": n, "theta": list(theta)}
+    res = {}
+    for prec in ("fp32c", "fp64"):
+        res[prec], wall, _, kms = time_steps(ctx, ds, theta, prec, True, 1, 1)
+        out[prec] = {"ms_per_call": wall * 1e3, "kernel_ms": kms, "pairs_per_s": float(n) * n / wall}
+    rows64 = ctx.rows(ds, theta, "fp64")
+    ds.close()
+    (e32, g32), (e64, g64) = res["fp32c"], res["fp64"]
+    l1 = np.abs(rows64["grad"]).sum(axis=0)
+    out["fp32c_vs_fp64"] = {"ell_rel": abs(e32 - e64) / abs(e64),
+                            "grad_plain_rel": (np.abs(g32 - g64) / np.abs(g64)).tolist(),
+                            "grad_l1_normalised": (np.abs(g32 - g64) / l1).tolist()}
+    xs, ys, ts = synth.subsample(x, y, t, 20000)
+    ds = ctx.dataset(xs, ys, ts)
+    sub = {prec: ctx.grad(ds, theta, prec) for prec in ("fp32c", "fp64")}
+    ds.close()
+    return out, (xs, ys, ts, theta, sub)
 
 
 def zero_skip_run(ctx, steps=10):
@@ -599,17 +665,24 @@ def main():
                      "traffic": measured_traffic(os.path.join(ROOT, "profiles", "pair_sym_fp32c_grad_city85k.json")),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0, copy-calibrated)",
                      "kernel": "pair_sym_fp32c<grad>", "kernel_ms": kms,
-                     "model": "1/(13.5 ops / 78.65e12 ops/s + 1.5 exp / 19.66e12 exp/s) per ordered pair (the "
-                              "method's work as in the direct enumeration): FP32 vector 157.3 TFLOP/s (FMA=2) and "
-                              "v_exp_f32 at 32 lanes/CU/clk x 256 CU x 2.4 GHz",
-                     "symmetric_model_frac": achieved / (1.0 / (WORK_SYM[0] / P_OPS32 + WORK_SYM[1] / P_EXP32)),
-                     "valu_tflops": achieved * 19.0 / 1e12},
+                     "model": "algorithmic work of the method per ordered pair (13.5 FP32 lane ops + 1.5 exp, as "
+                              "the direct enumeration evaluates it): 1/(13.5 / 78.65e12 ops/s + 1.5 / 19.66e12 exp/s); "
+                              "FP32 vector 157.3 TFLOP/s (FMA=2) and v_exp_f32 at 32 lanes/CU/clk x 256 CU x 2.4 GHz",
+                     "executed_work_peak": roofline_pairs(True, executed=True) / 1e9,
+                     "executed_work_frac": achieved / roofline_pairs(True, executed=True),
+                     "executed_work_model": "the work the symmetric pass executes per ordered pair (9 FP32 lane ops "
+                                            "+ 1 exp): 1/(9 / 78.65e12 + 1 / 19.66e12)",
+                     "method_tflops": achieved * 19.0 / 1e12},
         "p10_ms_step": float(np.percentile(per, 10) * 1e3),
         "p50_ms_step": float(np.percentile(per, 50) * 1e3),
         "p90_ms_step": float(np.percentile(per, 90) * 1e3),
         "p99_ms_step": float(np.percentile(per, 99) * 1e3),
         "fp64": {"pairs_per_s": pairs * steps64 / wall64, "ms_per_step": wall64 / steps64 * 1e3, "kernel_ms": kms64,
-                 "roofline_frac": (pairs / (kms64 * 1e-3)) / roofline_pairs(True, True)},
+                 # against the roofline of the work the symmetric FP64 pass executes (9 FP64 ops + one
+                 # 16-op exp2 per ordered pair at 78.6 TFLOP/s)
+                 "roofline_frac": (pairs / (kms64 * 1e-3)) / roofline_pairs(True, True, executed=True),
+                 "roofline_pairs_per_s": roofline_pairs(True, True, executed=True),
+                 "direct_enumeration_roofline_pairs_per_s": roofline_pairs(True, True)},
         "fp32c_vs_fp64": {"ell_rel": abs(ell - ell64) / abs(ell64),
                           "grad_l1_normalised": (np.abs(g - g64) / l1).tolist(),
                           "grad_plain_rel": (np.abs(g - g64) / np.abs(g64)).tolist()},
@@ -625,9 +698,12 @@ def main():
                              "pass ran back to back after the timed steps")
         result["roofline"]["clock"] = clk
     ds.close()
+    lw = sw = stw = None
     if not args.timing_only:
         result["posterior_regime"] = posterior_regime(ctx)
-        result["loglik_workload"] = loglik_workload(ctx)
+        result["loglik_workload"] = lw = loglik_workload(ctx)
+        result["small_workload"], sw = small_workload(ctx)
+        result["stress_workload"], stw = stress_workload(ctx)
         result["zero_tile_skip"] = zero_skip_run(ctx)
     if not args.no_shards:
         result["shard_share"] = shard_run(ctx)
@@ -648,10 +724,34 @@ def main():
         result["mcmc"] = mcmc_run(ctx)
     ctx.close()
     if not args.no_cpu_baseline:
+        import oracle
+
         result["cpu_baseline"] = cpu_baseline(x, y, t, theta)
+        result["cpu_baseline"].pop("per_row_s")
         result["cpu_baseline"]["gpu_speedup"] = value / result["cpu_baseline"]["value"]
-        result["cpu_all_cores"] = cpu_baseline_threads(x, y, t, theta, result["cpu_baseline"].pop("per_row_s"))
+        result["cpu_all_cores"], ref = cpu_all_cores_run(x, y, t, theta)
         result["cpu_all_cores"]["gpu_speedup"] = value / result["cpu_all_cores"]["value"]
+        # Every GPU result against the oracle's whole evaluation of its workload.
+        result["fp32c_vs_oracle"] = oracle_errors(ell, g, ref, theta)
+        result["fp64_vs_oracle"] = oracle_errors(ell64, g64, ref, theta)
+        if lw is not None:
+            ref2 = oracle.evaluate_parallel(*lw.pop("events"), lw["theta"])
+            for prec in ("fp32c", "fp64"):
+                lw[prec]["vs_oracle"] = oracle_errors(lw["ell"][prec], None, ref2, lw["theta"])
+        if sw is not None:
+            xs, ys, ts, ths = sw
+            ref1 = oracle.evaluate_parallel(xs, ys, ts, ths)
+            for prec in ("fp64", "fp32c"):
+                result["small_workload"][prec]["vs_oracle"] = oracle_errors(result["small_workload"][prec].pop("ell"),
+                                                                            None, ref1, ths)
+        if stw is not None:
+            xs, ys, ts, ths, sub = stw
+            ref5 = oracle.evaluate_parallel(xs, ys, ts, ths)
+            result["stress_workload"]["subsample_20k_vs_oracle"] = {
+                prec: oracle_errors(sub[prec][0], sub[prec][1], ref5, ths) for prec in ("fp32c", "fp64")}
+    if lw is not None:
+        lw.pop("events", None)
+        lw.pop("ell", None)
     torch.cuda.synchronize()
     print(json.dumps(result), flush=True)
 
