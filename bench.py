@@ -548,29 +548,81 @@ def pi_batch_run(ctx, n=55000, samples=64, seed=7):
             "mean_pi": float(pi.mean())}
 
 
-def mcmc_run(ctx, chains=4, steps=300, seed=11):
+PARAM_NAMES = ("mu0", "tau_x", "tau_t", "theta", "omega", "h")
+
+
+def mcmc_run(ctx, chains=4, steps=2000, hmc_iterations=300, hmc_warmup=100, seed=11):
     """The paper's sampler at its scale (Section 3.2: 4 chains of Algorithm 1 over the 85,000-event
-    data), run for `steps` states per chain through the serving API and extrapolated to 10,000
-    states per chain; FP32C log-likelihoods, with and without zero-tile skipping.  Data: the
-    15 x 15 km / 5,000-day workload; chains start near the paper's posterior parameters."""
+    data) for `steps` states per chain, and 4 HMC chains (leapfrog on log Theta with the fused
+    gradient) for `hmc_iterations` (the first `hmc_warmup` tune the step size and are not kept), both
+    through the serving API, with and without zero-tile skipping: evaluations/s, acceptance, and
+    per free parameter the effective sample size summed over chains (second half of each MH chain,
+    all kept HMC draws) and ESS/s.  Data: the 15 x 15 km / 5,000-day workload; chains start at its
+    generating parameters (tau_x, tau_t held fixed)."""
     from paper_2005_10123_amd import mcmc, synth
 
-    (x, y, t), _ = synth.config_events("city_85k_15km")
+    (x, y, t), theta0 = synth.config_events("city_85k_15km")
     ds = ctx.dataset(x, y, t)
-    out = {"workload": "city_85k_15km", "chains": chains, "steps_per_chain": steps}
+    out = {"workload": "city_85k_15km", "chains": chains, "mh_states_per_chain": steps,
+           "hmc_iterations": hmc_iterations, "hmc_warmup": hmc_warmup, "theta_start": list(theta0)}
+
+    def ess_report(ess, sec):
+        return {PARAM_NAMES[d]: {"ess": v, "ess_per_s": v / sec} for d, v in ess.items()}
+
     for skip in (False, True):
         ctx.set_zero_tile_skipping(skip)
-        chs = [mcmc.ChainState(np.array(THETA_POSTERIOR, float), np.random.default_rng(seed + k)) for k in range(chains)]
+        chs = [mcmc.ChainState(np.array(theta0, float), np.random.default_rng(seed + k)) for k in range(chains)]
         a = time.perf_counter()
         served = mcmc.run_served(ctx, chs, [ds] * chains, steps)
         sec = time.perf_counter() - a
-        out["zero_tile_skip" if skip else "all_pairs"] = {
-            "seconds": sec, "evaluations": served, "evaluations_per_s": served / sec,
-            "hours_per_10000_states_per_chain": sec / steps * 10000 / 3600,
-            "acceptance": float(np.mean([c.accepted / max(c.steps, 1) for c in chs]))}
+        mh = {"seconds": sec, "evaluations": served, "evaluations_per_s": served / sec,
+              "hours_per_10000_states_per_chain": sec / steps * 10000 / 3600,
+              "acceptance": float(np.mean([c.accepted / max(c.steps, 1) for c in chs])),
+              "ess": ess_report(mcmc.chain_ess(chs), sec)}
+        hch = [mcmc.HMCChain(np.array(theta0, float), np.random.default_rng(seed + 100 + k), warmup=hmc_warmup)
+               for k in range(chains)]
+        a = time.perf_counter()
+        served = mcmc.run_hmc_served(ctx, hch, [ds] * chains, hmc_iterations)
+        sec = time.perf_counter() - a
+        hmc = {"seconds": sec, "gradient_evaluations": served, "evaluations_per_s": served / sec,
+               "acceptance": float(np.mean([c.accepted / max(c.iters, 1) for c in hch])),
+               "step_size": [c.eps for c in hch], "ess": ess_report(mcmc.chain_ess(hch, 0.0), sec)}
+        out["zero_tile_skip" if skip else "all_pairs"] = {"mh": mh, "hmc": hmc}
     ctx.set_zero_tile_skipping(False)
     ds.close()
     return out
+
+
+def chain_serving_run(ctx, chains=256, datasets=16, iterations=5, seed=21):
+    """The serving workload driven by real samplers instead of synthetic arrivals: 256 HMC chains
+    (8 leapfrog steps, so 8 log-likelihood + gradient requests per iteration) over 16 resident
+    datasets of log-uniform size in [5,000, 120,000], chain k on dataset k mod 16, each keeping one
+    request in flight and submitting its next one as soon as its result is polled (closed loop, no
+    think time): p50/p99 latency and aggregate pairs/s."""
+    from paper_2005_10123_amd import mcmc, synth
+
+    sizes = synth.loguniform_sizes(datasets, 5e3, 1.2e5)
+    dss = [ctx.dataset(*synth.simulate(synth.SimSpec(n, 10.0, 1000.0, 3, 0.5, 0.1, 0.3, (10123, 4, d))))
+           for d, n in enumerate(sizes)]
+    rng = np.random.default_rng(seed)
+    theta0 = np.array(synth.THETA_CFG1)
+    chs = [mcmc.HMCChain(theta0 * np.exp(0.1 * rng.standard_normal(6)), np.random.default_rng(seed + k),
+                         warmup=iterations) for k in range(chains)]
+    lat, pairs = [], [0.0]
+
+    def record(k, r):
+        lat.append((r.t_done_ns - r.t_submit_ns) * 1e-9)
+        pairs[0] += float(sizes[k % datasets]) ** 2
+
+    a = time.perf_counter()
+    served = mcmc.run_hmc_served(ctx, chs, [dss[k % datasets] for k in range(chains)], iterations, on_result=record)
+    sec = time.perf_counter() - a
+    for d in dss:
+        d.close()
+    lat = np.array(lat)
+    return {"chains": chains, "datasets": datasets, "hmc_iterations": iterations, "requests": served,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p90_ms": float(np.percentile(lat, 90) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3), "pairs_per_s": pairs[0] / sec, "seconds": sec}
 
 
 def main():
@@ -720,6 +772,7 @@ def main():
         ctx.set_zero_tile_skipping(False)
         result["serving_zero_tile_skip"] = {k: r[k] for k in ("offered_utilisation", "requests", "p50_ms", "p90_ms",
                                                                "p99_ms", "pairs_per_s")}
+        result["serving_chains"] = chain_serving_run(ctx)
         result["pi_batch"] = pi_batch_run(ctx)
         result["mcmc"] = mcmc_run(ctx)
     ctx.close()

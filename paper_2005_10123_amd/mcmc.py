@@ -112,12 +112,13 @@ def run_local(loglik, theta0, steps: int, seed: int) -> ChainState:
     return ch
 
 
-def run_served(ctx, chains: list, datasets: list, steps: int, precision="fp32c", poll_us=200):
+def run_served(ctx, chains: list, datasets: list, steps: int, precision="fp32c", poll_us=200, on_result=None):
     """Advance many chains through the serving API until each has taken `steps` MH steps.
 
     chains[k] runs on datasets[k].  Each chain keeps one request in flight; a chain's next proposal
     is submitted as soon as its previous result is polled, so requests of different chains overlap
-    on the device.  Returns the number of requests served.
+    on the device.  ``on_result(k, result)``, if given, sees every polled result of chain k.
+    Returns the number of requests served.
     """
     from . import binding
 
@@ -135,6 +136,8 @@ def run_served(ctx, chains: list, datasets: list, steps: int, precision="fp32c",
             if r.status != 0:
                 raise RuntimeError(f"request {r.tag} failed with status {r.status}")
             k, is_prop = divmod(int(r.tag), 2)
+            if on_result is not None:
+                on_result(k, r)
             ch = chains[k]
             if is_prop:
                 ch.accept_reject(r.loglik)
@@ -145,6 +148,19 @@ def run_served(ctx, chains: list, datasets: list, steps: int, precision="fp32c",
                 continue
             ctx.submit([binding.request(datasets[k], ch.propose(), precision, want_grad=False, tag=2 * k + 1)])
     return served
+
+
+def chain_ess(chains: list, burn_fraction: float = 0.5) -> dict:
+    """ESS of each free coordinate summed over chains, each chain's samples after discarding the
+    first ``burn_fraction`` of them."""
+    out = {}
+    for d in FREE:
+        tot = 0.0
+        for ch in chains:
+            xs = np.array([s[d] for s in ch.samples])
+            tot += effective_sample_size(xs[int(burn_fraction * xs.size):])
+        out[d] = tot
+    return out
 
 
 def effective_sample_size(x: np.ndarray) -> float:
@@ -285,8 +301,10 @@ def run_hmc_local(loglik_grad, theta0, iterations: int, seed: int, **kw) -> HMCC
     return ch
 
 
-def run_hmc_served(ctx, chains: list, datasets: list, iterations: int, precision="fp32c", poll_us=200):
-    """Advance HMC chains through the serving API (one gradient request in flight per chain)."""
+def run_hmc_served(ctx, chains: list, datasets: list, iterations: int, precision="fp32c", poll_us=200,
+                   on_result=None):
+    """Advance HMC chains through the serving API (one gradient request in flight per chain);
+    ``on_result(k, result)``, if given, sees every polled result of chain k."""
     from . import binding
 
     gens = [ch.run(iterations) for ch in chains]
@@ -299,6 +317,8 @@ def run_hmc_served(ctx, chains: list, datasets: list, iterations: int, precision
             if r.status != 0:
                 raise RuntimeError(f"request {r.tag} failed with status {r.status}")
             k = int(r.tag)
+            if on_result is not None:
+                on_result(k, r)
             try:
                 th = gens[k].send((r.loglik, np.array(r.grad[:])))
             except StopIteration:
