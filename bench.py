@@ -152,6 +152,24 @@ def cpu_all_cores_run(x, y, t, theta):
                       f"ranges run concurrently"}, ref
 
 
+def host_simd_run(x, y, t, theta, ref):
+    """The library's host evaluation (hawkes_host_eval: the paper's multi-core CPU design with SIMD
+    loops, binary64, every ordered pair) on the whole workload over the host's cores (at most 16),
+    against the oracle's whole evaluation."""
+    from paper_2005_10123_amd import binding
+
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    n = x.size
+    binding.host_eval(x[:2000], y[:2000], t[:2000], theta, threads=threads)  # warm-up
+    a = time.perf_counter()
+    ell, g = binding.host_eval(x, y, t, theta, threads=threads)
+    sec = time.perf_counter() - a
+    return {"value": float(n) * n / sec, "unit": "pairs/s", "cores": threads, "seconds": sec,
+            "kind": "hawkes_host_eval (multi-core SIMD, binary64)",
+            "sample": f"all {n} events of the workload against all {n}",
+            "vs_oracle": oracle_errors(ell, g, ref, theta)}
+
+
 def cpu_model():
     """The host CPU's model name (first processor in /proc/cpuinfo), or None."""
     try:
@@ -787,6 +805,7 @@ def main():
         # Every GPU result against the oracle's whole evaluation of its workload.
         result["fp32c_vs_oracle"] = oracle_errors(ell, g, ref, theta)
         result["fp64_vs_oracle"] = oracle_errors(ell64, g64, ref, theta)
+        result["cpu_host_simd"] = host_simd_run(x, y, t, theta, ref)
         if lw is not None:
             ref2 = oracle.evaluate_parallel(*lw.pop("events"), lw["theta"])
             for prec in ("fp32c", "fp64"):

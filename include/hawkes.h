@@ -214,6 +214,22 @@ hawkes_status hawkes_set_pair_scheme(hawkes_ctx* ctx, int scheme);
  * hawkes_shard_sums. */
 hawkes_status hawkes_set_zero_tile_skipping(hawkes_ctx* ctx, int enable);
 
+/* ---- host evaluation ------------------------------------------------------------------------
+ * The paper's multi-core CPU design (Section 2.3; its CPU algorithms for the log-likelihood and the
+ * self-excitation probabilities): the events' rows are dealt to `threads` host threads, each
+ * keeping its row's coordinates in registers and running SIMD-vectorised loops over the other
+ * events (AVX-512, AVX2 or SSE2, chosen at load time) with running sums only; binary64 throughout,
+ * every ordered pair evaluated.  A separate evaluation on the host's cores, needing no context or
+ * device; no device entry point ever falls back to it.
+ *   x, y, t : n events in any order (host memory, copied; t >= 0, all finite); n >= 1
+ *   p       : Theta, validated as for hawkes_grad
+ *   threads : host threads to use (<= 0: as many as the hardware reports)
+ *   out7    : 7 doubles: ell, then d ell / d Theta
+ *   out_pi  : n doubles (pi_k in the caller's order), or NULL
+ * The result does not depend on `threads` (per-event terms summed in time order). */
+hawkes_status hawkes_host_eval(const double* x, const double* y, const double* t, int64_t n, const hawkes_params* p,
+                               int threads, double* out7, double* out_pi);
+
 /* ---- diagnostics -------------------------------------------------------------------------- */
 
 /* Thread-local message describing the calling thread's last failure ("" if none).  With the

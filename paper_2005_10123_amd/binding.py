@@ -105,6 +105,7 @@ def load(path: str | None = None):
         "hawkes_set_zero_tile_skipping": ([vp, ctypes.c_int], i32),
         "hawkes_loglik_multi": ([vp, i32, ctypes.POINTER(Params), i32, ctypes.c_int, _dp, _dp], i32),
         "hawkes_kernel_time": ([vp, _dp, ctypes.POINTER(i64), ctypes.c_int], i32),
+        "hawkes_host_eval": ([_dp, _dp, _dp, i64, ctypes.POINTER(Params), ctypes.c_int, _dp, _dp], i32),
         "hawkes_shard_sums": ([vp, i32, ctypes.POINTER(Params), ctypes.c_int, i32, i32, _dp], i32),
         "hawkes_finish": ([vp, i32, ctypes.POINTER(Params), _dp, _dp, _dp], i32),
     }
@@ -280,6 +281,23 @@ class Context:
         n = ctypes.c_int64()
         _check(self.lib.hawkes_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(n), 1 if reset else 0))
         return ms.value, n.value
+
+
+def host_eval(x, y, t, theta, threads=0, want_pi=False):
+    """hawkes_host_eval: (ell, gradient[6]) and, with want_pi, pi (n,) in the caller's order, on the
+    host's CPU cores (binary64, SIMD); needs no GPU."""
+    lib = load()
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    t = np.ascontiguousarray(t, dtype=np.float64)
+    if not (x.shape == y.shape == t.shape and x.ndim == 1):
+        raise ValueError("x, y, t must be 1-D arrays of equal length")
+    out = np.zeros(7)
+    pi = np.zeros(x.size) if want_pi else None
+    _check(lib.hawkes_host_eval(x.ctypes.data_as(_dp), y.ctypes.data_as(_dp), t.ctypes.data_as(_dp), x.size,
+                                ctypes.byref(params(theta)), int(threads), out.ctypes.data_as(_dp),
+                                pi.ctypes.data_as(_dp) if want_pi else None))
+    return (out[0], out[1:].copy(), pi) if want_pi else (out[0], out[1:].copy())
 
 
 def request(dataset, theta, precision="fp32c", want_grad=True, tag=0) -> Request:
