@@ -43,6 +43,14 @@ FP64_EXP_OPS = 16               # FP64 lane operations of one exp2 (range reduct
 KERNEL_SOURCES = ("hawkes_kernels.hip", "hawkes_device.h", "hawkes_internal.h")
 
 
+def leg(name, fn, *args, **kwargs):
+    """Run one part of the bench and note on stderr that it ended (the JSON line stays on stdout)."""
+    a = time.perf_counter()
+    r = fn(*args, **kwargs)
+    print(json.dumps({"done": name, "seconds": round(time.perf_counter() - a, 2)}), file=sys.stderr, flush=True)
+    return r
+
+
 def kernel_source_sha256() -> str:
     """sha256 over the code (comments and blank lines dropped) of the sources compiled into the
     pairwise kernels, in KERNEL_SOURCES order."""
@@ -703,9 +711,9 @@ def main():
     ctx = binding.Context(0)
     ds = ctx.dataset(x, y, t)
 
-    (ell, g), wall, per, kms = time_steps(ctx, ds, theta, "fp32c", True, args.steps, args.warmup)
+    (ell, g), wall, per, kms = leg("timed steps", time_steps, ctx, ds, theta, "fp32c", True, args.steps, args.warmup)
     steps64 = max(3, args.steps // 3)
-    (ell64, g64), wall64, per64, kms64 = time_steps(ctx, ds, theta, "fp64", True, steps64, 1)
+    (ell64, g64), wall64, per64, kms64 = leg("fp64 steps", time_steps, ctx, ds, theta, "fp64", True, steps64, 1)
     rows64 = ctx.rows(ds, theta, "fp64")
     l1 = np.abs(rows64["grad"]).sum(axis=0)
     pairs = float(n) * n
@@ -770,44 +778,44 @@ def main():
     ds.close()
     lw = sw = stw = None
     if not args.timing_only:
-        result["posterior_regime"] = posterior_regime(ctx)
-        result["loglik_workload"] = lw = loglik_workload(ctx)
-        result["small_workload"], sw = small_workload(ctx)
-        result["stress_workload"], stw = stress_workload(ctx)
-        result["zero_tile_skip"] = zero_skip_run(ctx)
+        result["posterior_regime"] = leg("posterior_regime", posterior_regime, ctx)
+        result["loglik_workload"] = lw = leg("loglik_workload", loglik_workload, ctx)
+        result["small_workload"], sw = leg("small_workload", small_workload, ctx)
+        result["stress_workload"], stw = leg("stress_workload", stress_workload, ctx)
+        result["zero_tile_skip"] = leg("zero_tile_skip", zero_skip_run, ctx)
     if not args.no_shards:
-        result["shard_share"] = shard_run(ctx)
+        result["shard_share"] = leg("shard_share", shard_run, ctx)
     if not args.no_serving:
-        result["serving"] = serving_run(ctx, seconds=args.serving_seconds)
+        result["serving"] = leg("serving", serving_run, ctx, seconds=args.serving_seconds)
         result["serving_sweep"] = []
         for u in (0.5, 1.0, 2.0):
-            r = serving_run(ctx, seconds=3.0, utilisation=u, min_requests=0)
+            r = leg(f"serving_sweep {u}", serving_run, ctx, seconds=3.0, utilisation=u, min_requests=0)
             result["serving_sweep"].append({k: r[k] for k in ("offered_utilisation", "requests", "p50_ms", "p99_ms",
                                                               "pairs_per_s")})
         # The same closed loop with zero-tile skipping on (capacity re-estimated with it on).
         ctx.set_zero_tile_skipping(True)
-        r = serving_run(ctx, seconds=4.0, min_requests=5000)
+        r = leg("serving_zero_tile_skip", serving_run, ctx, seconds=4.0, min_requests=5000)
         ctx.set_zero_tile_skipping(False)
         result["serving_zero_tile_skip"] = {k: r[k] for k in ("offered_utilisation", "requests", "p50_ms", "p90_ms",
                                                                "p99_ms", "pairs_per_s")}
-        result["serving_chains"] = chain_serving_run(ctx)
-        result["pi_batch"] = pi_batch_run(ctx)
-        result["mcmc"] = mcmc_run(ctx)
+        result["serving_chains"] = leg("serving_chains", chain_serving_run, ctx)
+        result["pi_batch"] = leg("pi_batch", pi_batch_run, ctx)
+        result["mcmc"] = leg("mcmc", mcmc_run, ctx)
     ctx.close()
     if not args.no_cpu_baseline:
         import oracle
 
-        result["cpu_baseline"] = cpu_baseline(x, y, t, theta)
+        result["cpu_baseline"] = leg("cpu_baseline", cpu_baseline, x, y, t, theta)
         result["cpu_baseline"].pop("per_row_s")
         result["cpu_baseline"]["gpu_speedup"] = value / result["cpu_baseline"]["value"]
-        result["cpu_all_cores"], ref = cpu_all_cores_run(x, y, t, theta)
+        result["cpu_all_cores"], ref = leg("cpu_all_cores", cpu_all_cores_run, x, y, t, theta)
         result["cpu_all_cores"]["gpu_speedup"] = value / result["cpu_all_cores"]["value"]
         # Every GPU result against the oracle's whole evaluation of its workload.
         result["fp32c_vs_oracle"] = oracle_errors(ell, g, ref, theta)
         result["fp64_vs_oracle"] = oracle_errors(ell64, g64, ref, theta)
-        result["cpu_host_simd"] = host_simd_run(x, y, t, theta, ref)
+        result["cpu_host_simd"] = leg("cpu_host_simd", host_simd_run, x, y, t, theta, ref)
         if lw is not None:
-            ref2 = oracle.evaluate_parallel(*lw.pop("events"), lw["theta"])
+            ref2 = leg("oracle loglik_workload", oracle.evaluate_parallel, *lw.pop("events"), lw["theta"])
             for prec in ("fp32c", "fp64"):
                 lw[prec]["vs_oracle"] = oracle_errors(lw["ell"][prec], None, ref2, lw["theta"])
         if sw is not None:
@@ -818,7 +826,7 @@ def main():
                                                                             None, ref1, ths)
         if stw is not None:
             xs, ys, ts, ths, sub = stw
-            ref5 = oracle.evaluate_parallel(xs, ys, ts, ths)
+            ref5 = leg("oracle stress subsample", oracle.evaluate_parallel, xs, ys, ts, ths)
             result["stress_workload"]["subsample_20k_vs_oracle"] = {
                 prec: oracle_errors(sub[prec][0], sub[prec][1], ref5, ths) for prec in ("fp32c", "fp64")}
     if lw is not None:
