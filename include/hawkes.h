@@ -109,6 +109,21 @@ hawkes_status hawkes_grad(hawkes_ctx* ctx, int32_t id, const hawkes_params* p, i
 hawkes_status hawkes_grad_device(hawkes_ctx* ctx, int32_t id, const hawkes_params* p, int precision,
                                  double* d_out7, void* hip_stream);
 
+/* hawkes_grad_device for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments, kernels, plan and result
+ * as hawkes_grad_device (bitwise), but the evaluation scratch is a fixed 256 MiB device array that
+ * the library holds on every device it runs on until the process ends, not memory of the context:
+ * this call makes no device or host allocation (its address is looked up once per device by
+ * hawkes_create).  Limit: an evaluation whose scratch exceeds 256 MiB fails with HAWKES_ENOMEM
+ * before anything is enqueued (symmetric enumeration: up to about 200,000 events with FP32C, about
+ * 130,000 with FP64; the direct enumeration's scratch grows linearly in n).  Every call on one GPU,
+ * from any context or thread, shares that array: calls whose device work overlaps (different
+ * streams not ordered with each other, or another context on the same GPU) race and give wrong
+ * results; calls on one stream, or on streams the caller orders, are safe.  The array keeps the
+ * last call's contents; nothing in it needs clearing between calls. */
+hawkes_status hawkes_grad_device_noalloc(hawkes_ctx* ctx, int32_t id, const hawkes_params* p, int precision,
+                                         double* d_out7, void* hip_stream);
+
 /* Blocking per-event results in the caller's original order: for event k, out_rows[10k + f] with
  * f = 0 lambda_k, 1 Lambda_k, 2 ell_k = log lambda_k - Lambda_k, 3 pi_k (self-excitation
  * probability), 4..9 d ell_k / d Theta.  out_rows holds n * HAWKES_ROW_FIELDS doubles. */

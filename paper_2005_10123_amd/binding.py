@@ -95,6 +95,7 @@ def load(path: str | None = None):
         "hawkes_loglik": ([vp, i32, ctypes.POINTER(Params), ctypes.c_int, _dp], i32),
         "hawkes_grad": ([vp, i32, ctypes.POINTER(Params), ctypes.c_int, _dp, _dp], i32),
         "hawkes_grad_device": ([vp, i32, ctypes.POINTER(Params), ctypes.c_int, vp, vp], i32),
+        "hawkes_grad_device_noalloc": ([vp, i32, ctypes.POINTER(Params), ctypes.c_int, vp, vp], i32),
         "hawkes_rows": ([vp, i32, ctypes.POINTER(Params), ctypes.c_int, _dp], i32),
         "hawkes_submit": ([vp, ctypes.POINTER(Request), i32], i32),
         "hawkes_poll": ([vp, ctypes.POINTER(Result), i32, ctypes.POINTER(i32), i64], i32),
@@ -237,6 +238,12 @@ class Context:
         """Enqueue on the hipStream_t `stream_ptr` (0: the null stream)."""
         _check(self.lib.hawkes_grad_device(self._h, _id(ds), ctypes.byref(params(theta)), _prec(precision),
                                            ctypes.c_void_p(d_out7_ptr), ctypes.c_void_p(stream_ptr or None)))
+
+    def grad_device_noalloc(self, ds, theta, precision, d_out7_ptr: int, stream_ptr=0):
+        """hawkes_grad_device with the library's fixed device scratch (no allocation); enqueued on
+        the hipStream_t `stream_ptr` (0: the null stream)."""
+        _check(self.lib.hawkes_grad_device_noalloc(self._h, _id(ds), ctypes.byref(params(theta)), _prec(precision),
+                                                   ctypes.c_void_p(d_out7_ptr), ctypes.c_void_p(stream_ptr or None)))
 
     def info(self, ds):
         n = ctypes.c_int64()

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIBRARY = os.path.join(HERE, "libhawkes.so")
 RATES_PROBE = os.path.join(HERE, "rates_probe")
-SOURCES = ["hawkes_kernels.hip", "hawkes_runtime.hip", "hawkes_serving.hip", "hawkes_multi.hip", "hawkes_shard.hip", "hawkes_epilogue.hip", "hawkes_host.hip"]
+SOURCES = ["hawkes_kernels.hip", "hawkes_runtime.hip", "hawkes_serving.hip", "hawkes_multi.hip", "hawkes_shard.hip", "hawkes_epilogue.hip", "hawkes_host.hip", "hawkes_noalloc.hip"]
 ARCH = "gfx950"
 # Packed FP32 VALU forms are switched off for all device code on this target.
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",

@@ -125,9 +125,20 @@ hawkes_status poison(hawkes_ctx* c, hawkes_status st);
 // Adds the last profiled pair-kernel time once the stream has passed it.
 void collect_profile(hawkes_ctx* c);
 hawkes_status reserve_blocking(hawkes_ctx* c, size_t need);
+// Enqueue one evaluation (pairwise pass, epilogue, final reduction) on stream s with its scratch
+// carved from `scratch`; out7_override (device, 7 doubles) replaces the scratch's result slot.
+hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params& p, int precision, bool grad,
+                           char* scratch, double* out7_override, double** out7_used, double** rows_out,
+                           bool want_rows, hipStream_t s);
 hawkes_status blocking_eval(hawkes_ctx* c, int32_t id, const hawkes_params* p, int precision, bool grad,
                             double out7[7], double* host_rows);
 int multi_blocks_per_cu();
+
+// hawkes_grad_device_noalloc: the fixed device array holding its evaluation scratch (256 MiB on
+// every device the library runs on), and the per-device lookup of that array's address, done once
+// per device by hawkes_create with the device current.
+constexpr size_t kNoallocScratchBytes = (size_t)256 << 20;
+hawkes_status noalloc_init(int device);
 
 hawkes_status server_start(hawkes_ctx* c);
 void server_stop(hawkes_ctx* c);

@@ -569,7 +569,9 @@ hawkes_status hawkes_create(int device, size_t hbm_budget_bytes, void* hip_strea
     for (int prec = 0; prec < 2; ++prec)
         for (int g = 0; g < 2; ++g) c->sym_slots[prec][g] = cus * sym_blocks_per_cu(prec, g != 0);
     c->multi_slots = cus * multi_blocks_per_cu();
-    hawkes_status st = server_start(c.get());
+    hawkes_status st = noalloc_init(device);
+    if (st != HAWKES_OK) return st;
+    st = server_start(c.get());
     if (st != HAWKES_OK) return st;
     *out = c.release();
     return HAWKES_OK;

@@ -262,6 +262,9 @@ int sym_blocks_per_cu(int precision, bool) { return precision == 0 ? 2 : 3; }
 
 int multi_blocks_per_cu() { return 2; }
 
+// The fixed-scratch entry point (hawkes_noalloc.hip) is device code only; its set-up call is a no-op here.
+int32_t noalloc_init(int) { return 0; }
+
 hipError_t launch_epilogue(const EpiBatch& b, hipStream_t)
 {
     const double log2e = 1.44269504088896340736;
