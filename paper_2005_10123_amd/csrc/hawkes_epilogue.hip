@@ -62,6 +62,84 @@ __device__ __forceinline__ void column_totals(const T* __restrict__ pc, long lon
     for (int q = 0; q < KC; ++q) S[q] += (acc[q][0] + acc[q][1]) + (acc[q][2] + acc[q][3]);
 }
 
+// The walk positions [lo, hi) of row block I's units in the symmetric pass (the walked units with
+// zero-tile skipping), the walk's split, and the dynamic-tail chunks [cf, cl] holding some of them
+// (cl < cf: none).
+struct RowBlockWalk {
+    long long lo, hi;
+    WalkSplit ws;
+    long long cf, cl;
+};
+
+__device__ __forceinline__ RowBlockWalk row_block_walk(const EpiReq& rq, int I)
+{
+    constexpr long long TB = kRowsPerBlock / kTile;
+    RowBlockWalk r;
+    long long units;
+    if (rq.zcum) {
+        units = rq.zcum[rq.row_blocks];
+        r.lo = rq.zcum[I];
+        r.hi = rq.zcum[I + 1];
+    } else {
+        units = rq.uend - rq.ubegin;
+        r.lo = max(TB * I * (I + 1) / 2, rq.ubegin) - rq.ubegin;
+        r.hi = min(TB * (I + 1) * (I + 2) / 2, rq.uend) - rq.ubegin;
+    }
+    r.ws = walk_split(units, rq.pair_items, rq.dchunks);
+    r.cf = 0;
+    r.cl = -1;
+    const long long dlo = max(r.lo, r.ws.sunits);
+    if (dlo < r.hi) {
+        r.cf = split_block(dlo - r.ws.sunits, r.ws.cbase, r.ws.crem);
+        r.cl = split_block(r.hi - 1 - r.ws.sunits, r.ws.cbase, r.ws.crem);
+    }
+    return r;
+}
+
+// Row partials of the dynamic-tail chunks: per row block that several chunks walked, their sums
+// in chunk order are folded into the first chunk's slot, so the epilogue reads one slot for them.
+// A block takes one (row block, quantity, 64 rows): its kFoldWaves waves take every
+// kFoldWaves-th chunk (four running sums each, combined in a fixed order), lanes are consecutive
+// rows (coalesced), and the waves' sums are added in wave order.  Every element is read and
+// written by one block only, so the fold is in place; the result depends only on the plan.
+constexpr int kFoldWaves = 8;
+constexpr int kFoldGroups = kRowsPerBlock / 64;
+
+__global__ __launch_bounds__(kFoldWaves * 64) void dyn_fold(const EpiReq rq, int first_row_block)
+{
+    __shared__ double wsum[kFoldWaves][64];
+    const int K = rq.grad ? 6 : 2;
+    const int per_block = kFoldGroups * K;
+    const int I = first_row_block + (int)blockIdx.x / per_block;
+    const int k = ((int)blockIdx.x % per_block) / kFoldGroups, g = (int)blockIdx.x % kFoldGroups;
+    const RowBlockWalk rw = row_block_walk(rq, I);
+    if (rw.cl <= rw.cf) return;  // no chunk, or one: nothing to fold (uniform over the block)
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const size_t stride = (size_t)K * kRowsPerBlock;
+    const double* src = rq.part + (size_t)(rq.pair_items + rq.row_blocks + I) * stride + (size_t)k * kRowsPerBlock +
+                        g * 64 + lane;  // + c * stride: chunk c's value
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    long long c = rw.cf + w;
+    constexpr int W = kFoldWaves;
+    for (; c + 3 * W <= rw.cl; c += 4 * W) {
+        const double v0 = src[(size_t)c * stride], v1 = src[(size_t)(c + W) * stride];
+        const double v2 = src[(size_t)(c + 2 * W) * stride], v3 = src[(size_t)(c + 3 * W) * stride];
+        a0 += v0;
+        a1 += v1;
+        a2 += v2;
+        a3 += v3;
+    }
+    for (; c <= rw.cl; c += W) a0 += src[(size_t)c * stride];
+    wsum[w][lane] = (a0 + a1) + (a2 + a3);
+    __syncthreads();
+    if (w == 0) {
+        double t = wsum[0][lane];
+#pragma unroll
+        for (int v = 1; v < kFoldWaves; ++v) t += wsum[v][lane];
+        const_cast<double*>(src)[(size_t)rw.cf * stride] = t;
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
 {
     __shared__ double red[7][kThreads];
@@ -78,36 +156,28 @@ __global__ __launch_bounds__(kThreads) void epilogue(const EpiBatch batch)
 #pragma unroll
             for (int k = 0; k < 6; ++k) S[k] = rq.sums_in[(size_t)i * 6 + k];
         } else if (rq.scheme == kSymmetric) {
-            // Row sums: one partial per block that walked a unit of this row block, in block order.
-            constexpr long long TB = kRowsPerBlock / kTile;
+            // Row sums: one partial per static range (block) that walked a unit of this row block,
+            // in block order, then the dynamic-tail chunks' (folded into the first one's slot).
             const int I = i / kRowsPerBlock, rho = i % kRowsPerBlock;
-            long long lo, hi, ubegin, ubase, urem;
-            if (rq.zcum) {  // zero-tile skipping: the walked units and their even split
-                const long long units = rq.zcum[rq.row_blocks];
-                ubegin = 0;
-                ubase = units / rq.pair_items;
-                urem = units % rq.pair_items;
-                lo = rq.zcum[I];
-                hi = rq.zcum[I + 1];
-            } else {
-                ubegin = rq.ubegin;
-                ubase = rq.ubase;
-                urem = rq.urem;
-                lo = max(TB * I * (I + 1) / 2, rq.ubegin);
-                hi = min(TB * (I + 1) * (I + 2) / 2, rq.uend);
+            const RowBlockWalk rw = row_block_walk(rq, I);
+            const long long shi = min(rw.hi, rw.ws.sunits);
+            long long nslot = 0;
+            long long slots[2] = {0, 0};  // static: [bf, bl] + I; then the folded dynamic slot
+            long long bf = 0, bl = -1;
+            if (rw.lo < shi) {
+                bf = split_block(rw.lo, rw.ws.sbase, rw.ws.srem);
+                bl = split_block(shi - 1, rw.ws.sbase, rw.ws.srem);
             }
-            if (lo < hi) {
-                const long long bf = split_block(lo - ubegin, ubase, urem);
-                const long long bl = split_block(hi - 1 - ubegin, ubase, urem);
-                for (long long b = bf; b <= bl; ++b) {
-                    const double* ps = rq.part + (size_t)(b + I) * K * kRowsPerBlock + rho;
-                    if (rq.grad) {
+            if (rw.cl >= rw.cf) slots[nslot++] = rq.pair_items + rq.row_blocks + rw.cf + I;
+            for (long long m = 0; m < (bl - bf + 1) + nslot; ++m) {
+                const long long slot = m <= bl - bf ? bf + m + I : slots[m - (bl - bf + 1)];
+                const double* ps = rq.part + (size_t)slot * K * kRowsPerBlock + rho;
+                if (rq.grad) {
 #pragma unroll
-                        for (int k = 0; k < 6; ++k) S[k] += ps[(size_t)k * kRowsPerBlock];
-                    } else {
-                        S[0] += ps[0];
-                        S[3] += ps[kRowsPerBlock];
-                    }
+                    for (int q6 = 0; q6 < 6; ++q6) S[q6] += ps[(size_t)q6 * kRowsPerBlock];
+                } else {
+                    S[0] += ps[0];
+                    S[3] += ps[kRowsPerBlock];
                 }
             }
             // Column sums: the background terms with every later event, by row block J >= I, from
@@ -224,6 +294,23 @@ __global__ __launch_bounds__(kThreads) void final_sum(const EpiBatch batch)
 hipError_t launch_epilogue(const EpiBatch& b, hipStream_t s)
 {
     if (b.total_items <= 0) return hipSuccess;
+    for (int q = 0; q < b.nreq; ++q) {
+        const EpiReq& r = b.r[q];
+        if (r.scheme != kSymmetric || r.dchunks <= 0 || r.sums_in) continue;
+        // Row blocks that may hold dynamic-tail chunks: with zero-tile skipping any (the walked
+        // units are known on the device only); otherwise those ending after the static part.
+        int first = 0;
+        if (!r.zcum) {
+            constexpr long long TB = kRowsPerBlock / kTile;
+            const WalkSplit ws = walk_split(r.uend - r.ubegin, r.pair_items, r.dchunks);
+            while (first < r.row_blocks && TB * (first + 1) * (first + 2) / 2 - r.ubegin <= ws.sunits) ++first;
+        }
+        if (first >= r.row_blocks) continue;
+        const int K = r.grad ? 6 : 2;
+        dyn_fold<<<dim3((r.row_blocks - first) * kFoldGroups * K), dim3(kFoldWaves * 64), 0, s>>>(r, first);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     epilogue<<<dim3(b.total_items), dim3(kThreads), 0, s>>>(b);
     return hipGetLastError();
 }

@@ -57,6 +57,10 @@ struct PairReq {
     int item_begin;       // first work item (block) of this request in the launch
     int items;            // work items (blocks) of this request
     int balance;          // symmetric: 1 when the launch has the device to itself (progress priority)
+    // Symmetric: the walk's dynamic tail (dev::walk_split): at most dchunks chunks taken from the
+    // counter *ctr (zero when the pass starts; 0 chunks: a static split only).
+    int dchunks;
+    unsigned long long* ctr;
     // Zero-tile skipping (symmetric scheme; nullptr when off): zcum[I], I <= row_blocks, is the
     // number of walked units in the row blocks before I, followed by zskip[I] (int), the leading
     // column tiles of row block I that are not walked: every pair term there is exactly zero
@@ -99,6 +103,7 @@ struct EpiReq {
     int nblocks;          // ceil(n / kThreads)
     int item_begin;
     int pair_items;          // blocks of the pairwise pass (symmetric: the walk's split)
+    int dchunks;             // symmetric: the walk's dynamic tail, as in PairReq
     const long long* zcum;   // zero-tile skipping: as in PairReq, or nullptr
     double T;             // largest event time
     double mu0, tau_x, tau_t, theta, omega, h;
@@ -111,6 +116,42 @@ struct EpiBatch {
     int nreq;
     int total_items;
 };
+
+// Dynamic tail of the symmetric walk.  Run-time speed differs between compute units (the
+// graphics clock of each XCD, the waves sharing a SIMD), so an even static split of the work units
+// leaves some units idle at the end.  The last 1/kDynDiv of the walked units are cut into at most
+// PairReq::dchunks contiguous chunks that blocks take from a counter once their own static range
+// is done.  Each chunk writes its own row partial sums (slot items + row_blocks + c + I for chunk c
+// and row block I; a static range b writes slot b + I), so which block runs a chunk changes neither
+// the arithmetic nor the summation order, and the result stays deterministic.
+constexpr long long kDynDiv = 8;
+constexpr long long kDynMinUnitsPerBlock = 4;  // smaller walks keep the static split only
+constexpr int kDynChunksPerBlock = 2;          // the host plan's cap on dchunks, per block
+
+struct WalkSplit {
+    long long sunits;       // walk positions [0, sunits) are dealt statically: block b walks
+    long long sbase, srem;  // [b sbase + min(b, srem), (b + 1) sbase + min(b + 1, srem))
+    long long chunks;       // positions [sunits, units) in `chunks` chunks, split the same way
+    long long cbase, crem;
+};
+
+__host__ __device__ inline WalkSplit walk_split(long long units, int items, int dchunks)
+{
+    WalkSplit w = {0, 0, 0, 0, 0, 0};
+    if (items <= 0 || units <= 0) return w;
+    long long d = (dchunks > 0 && units >= kDynMinUnitsPerBlock * items) ? units / kDynDiv : 0;
+    const long long ch = d < (long long)dchunks ? d : (long long)dchunks;
+    if (ch <= 0) d = 0;
+    w.sunits = units - d;
+    w.sbase = w.sunits / items;
+    w.srem = w.sunits % items;
+    if (ch > 0) {
+        w.chunks = ch;
+        w.cbase = d / ch;
+        w.crem = d % ch;
+    }
+    return w;
+}
 
 // Kernel arguments are passed by value; keep them within 4 KiB.
 static_assert(sizeof(PairBatch) <= 4096 && sizeof(EpiBatch) <= 4096, "kernel argument block too large");

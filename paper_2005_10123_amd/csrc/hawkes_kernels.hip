@@ -485,6 +485,7 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
     __shared__ float comp_lds[K * R * NT];
     __shared__ float red_lds[kSymWaves][4 * 64];
     volatile lds_float* comp = (lds_float*)comp_lds + threadIdx.x;
+    __shared__ long long next_chunk;
 
     const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
     const PairReq& rq = batch.r[q];
@@ -492,13 +493,15 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = rq.n;
-    const SymWalk walk = sym_walk_begin(rq, blk);
-    long long u = walk.u;
-    const long long uend = walk.uend;
-    const long long ubeg = u;
+    // Walk positions: without zero-tile skipping, units ubegin + position of the lower triangle;
+    // with it, the walked units (zcum) from 0.  The block's static range first, then chunks of the
+    // dynamic tail (walk_split) while any are left.
+    const long long walk0 = ZSKIP ? 0 : rq.ubegin;
+    const WalkSplit ws = walk_split(ZSKIP ? rq.zcum[rq.row_blocks] : rq.units, rq.items, rq.dchunks);
+    long long r0 = split_begin(blk, ws.sbase, ws.srem), r1 = split_begin(blk + 1, ws.sbase, ws.srem);
+    const long long static_len = r1 - r0;
+    int slot0 = blk;  // row partials of row block I go to slot slot0 + I
     int prio = -1;
-    int I = walk.I;
-    int kw = walk.k;  // position of the current unit among row block I's walked tiles
 
     const float tsh = in_vgpr(rq.tsh), tsl = in_vgpr(rq.tsl), nab = in_vgpr(rq.nab);
     const float nae = in_vgpr(rq.nae), kte = in_vgpr(rq.kte);
@@ -510,146 +513,173 @@ __global__ __launch_bounds__(kSymThreads) __attribute__((amdgpu_waves_per_eu(kSy
     float ti[R];           // the rows' times since the current far tile's first event
     float th[R], tl[R];    // the rows' hi/lo times (kept across tiles without the gradient)
 
-    for (; u < uend; ++u) {
-        if (rq.balance) progress_priority(u - ubeg, uend - ubeg, prio);
-        if (I != cur) {
-            if (cur >= 0) {
-#pragma unroll
-                for (int k = 0; k < K; ++k)
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
-                            (double)s[k][r] + (double)comp[(k * R + r) * NT];
-            }
-            cur = I;
-            w0 = I * kRowsPerBlock + wave * (64 * R);
-            lrow0 = w0 + R * lane;
-            active = w0 < n;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = lrow0 + r;
-                const float4 a = rq.ev32[2 * (size_t)i];
-                const float4 b = rq.ev32[2 * (size_t)i + 1];
-                xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
-                th[r] = a.z;
-                tl[r] = b.z;
-            }
-            t_first = uniform(rq.ev32[2 * (size_t)min(w0, n - 1)].z + rq.ev32[2 * (size_t)min(w0, n - 1) + 1].z);
-            clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-#pragma unroll
-                for (int r = 0; r < R; ++r) s[k][r] = 0.0f;
-#pragma unroll
-            for (int k = 0; k < K * R; ++k) comp[k * NT] = 0.0f;
-        }
-        const int tile = ZSKIP ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
-        const int j0 = tile * kTile;
-        __syncthreads();
-        {
-            // Each column's scaled time since the tile's first event goes into the .w of its hi
-            // part (read by far tiles only).
-            const float c0h = rq.ev32[2 * (size_t)j0].z, c0l = rq.ev32[2 * (size_t)j0 + 1].z;
-#pragma unroll
-            for (int c = threadIdx.x; c < kTile; c += NT) {
-                const float4* src = rq.ev32 + 2 * (size_t)(j0 + c);
-                float4 hi = src[0];
-                const float4 lo = src[1];
-                const float tu = (hi.z - c0h) + (lo.z - c0l);
-                hi.w = fmaf(tu, tsh, tu * tsl);
-                sj[2 * c] = hi;
-                sj[2 * c + 1] = lo;
+    for (long long chunk = -1;;) {
+        long long u = walk0 + r0;
+        const long long uend = walk0 + r1;
+        int I = 0, kw = 0;  // the current unit: the kw-th walked tile of row block I
+        if (u < uend) {
+            if (ZSKIP) {
+                I = zero_row_block(rq.zcum, rq.row_blocks, u);
+                kw = (int)(u - rq.zcum[I]);
+            } else {
+                I = sym_row_block(u);
+                kw = (int)(u - sym_unit0(I));
             }
         }
-        __syncthreads();
-        int mode;
-        if (!active || j0 >= w0 + 64 * R) mode = kSkip;
-        else if (j0 + kTile <= w0) mode = (j0 + kTile <= clo) ? kFullLow : kMaskLow;
-        else mode = kDiag;
-        float* colw = &colred[wave][0][0];
-        if (mode == kSkip) {
+        cur = -1;
+        for (; u < uend; ++u) {
+            // Static range: priority from the block's progress through it; dynamic chunks: lowest.
+            if (rq.balance) progress_priority(chunk < 0 ? u - walk0 - r0 : static_len, static_len, prio);
+            if (I != cur) {
+                if (cur >= 0) {
 #pragma unroll
-            for (int qq = 0; qq < KC; ++qq)
+                    for (int k = 0; k < K; ++k)
 #pragma unroll
-                for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
-        } else if (mode == kFullLow && far_tile_by_span(sj, t_first)) {
-            if (GRAD) {  // short of registers: the row times are reloaded rather than kept
+                        for (int r = 0; r < R; ++r)
+                            rq.part[((size_t)(slot0 + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
+                                (double)s[k][r] + (double)comp[(k * R + r) * NT];
+                }
+                cur = I;
+                w0 = I * kRowsPerBlock + wave * (64 * R);
+                lrow0 = w0 + R * lane;
+                active = w0 < n;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    th[r] = rq.ev32[2 * (size_t)(lrow0 + r)].z;
-                    tl[r] = rq.ev32[2 * (size_t)(lrow0 + r) + 1].z;
+                    const int i = lrow0 + r;
+                    const float4 a = rq.ev32[2 * (size_t)i];
+                    const float4 b = rq.ev32[2 * (size_t)i + 1];
+                    xh[r] = a.x; yh[r] = a.y; xl[r] = b.x; yl[r] = b.y;
+                    th[r] = a.z;
+                    tl[r] = b.z;
+                }
+                t_first = uniform(rq.ev32[2 * (size_t)min(w0, n - 1)].z + rq.ev32[2 * (size_t)min(w0, n - 1) + 1].z);
+                clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) s[k][r] = 0.0f;
+#pragma unroll
+                for (int k = 0; k < K * R; ++k) comp[k * NT] = 0.0f;
+            }
+            const int tile = ZSKIP ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
+            const int j0 = tile * kTile;
+            __syncthreads();
+            {
+                // Each column's scaled time since the tile's first event goes into the .w of its hi
+                // part (read by far tiles only).
+                const float c0h = rq.ev32[2 * (size_t)j0].z, c0l = rq.ev32[2 * (size_t)j0 + 1].z;
+#pragma unroll
+                for (int c = threadIdx.x; c < kTile; c += NT) {
+                    const float4* src = rq.ev32 + 2 * (size_t)(j0 + c);
+                    float4 hi = src[0];
+                    const float4 lo = src[1];
+                    const float tu = (hi.z - c0h) + (lo.z - c0l);
+                    hi.w = fmaf(tu, tsh, tu * tsl);
+                    sj[2 * c] = hi;
+                    sj[2 * c + 1] = lo;
                 }
             }
-            tile_times(th, tl, sj[0].z, sj[1].z, tsh, tsl, ti);
-            const int ct[R] = {};  // not read: every column of the tile is causal for every row
-            int far_mode = kFullLow;
-            if (ZSKIP) {
-                // Every pair of the tile is at least `gap` apart in time.
-                const float gap = uniform(t_first - (sj[2 * (kTile - 1)].z + sj[2 * (kTile - 1) + 1].z));
-                const bool no_b = gap >= rq.zero_gap_b, no_e = gap >= rq.zero_gap_e;
-                far_mode = no_b ? (no_e ? kSkip : kFullLowE) : (no_e ? kFullLowB : kFullLow);
-            }
-            if (far_mode == kFullLow)
-                sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, tsh, tsl,
-                                                     nab, nae, kte, s, comp, colw, red_lds[wave], lane);
-            else if (far_mode == kFullLowB)
-                sym_tile_fp32<kFullLowB, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, tsh, tsl,
-                                                      nab, nae, kte, s, comp, colw, red_lds[wave], lane);
-            else if (far_mode == kFullLowE)
-                sym_tile_fp32<kFullLowE, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, tsh, tsl,
-                                                      nab, nae, kte, s, comp, colw, red_lds[wave], lane);
-            else
+            __syncthreads();
+            int mode;
+            if (!active || j0 >= w0 + 64 * R) mode = kSkip;
+            else if (j0 + kTile <= w0) mode = (j0 + kTile <= clo) ? kFullLow : kMaskLow;
+            else mode = kDiag;
+            float* colw = &colred[wave][0][0];
+            if (mode == kSkip) {
 #pragma unroll
                 for (int qq = 0; qq < KC; ++qq)
 #pragma unroll
                     for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
-        } else {
-            // Tiles that straddle the rows' causal counts or their own positions, and causal tiles
-            // closer in time to the rows than kNearTiles tile spans (taken by the masked path, whose
-            // masks then pass every pair): exact time differences, from the row times loaded here.
-            int ct[R];
+            } else if (mode == kFullLow && far_tile_by_span(sj, t_first)) {
+                if (GRAD) {  // short of registers: the row times are reloaded rather than kept
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                ct[r] = rq.cut[lrow0 + r];
-                if (GRAD) {  // short of registers: reloaded here rather than kept
-                    th[r] = rq.ev32[2 * (size_t)(lrow0 + r)].z;
-                    tl[r] = rq.ev32[2 * (size_t)(lrow0 + r) + 1].z;
+                    for (int r = 0; r < R; ++r) {
+                        th[r] = rq.ev32[2 * (size_t)(lrow0 + r)].z;
+                        tl[r] = rq.ev32[2 * (size_t)(lrow0 + r) + 1].z;
+                    }
+                }
+                tile_times(th, tl, sj[0].z, sj[1].z, tsh, tsl, ti);
+                const int ct[R] = {};  // not read: every column of the tile is causal for every row
+                int far_mode = kFullLow;
+                if (ZSKIP) {
+                    // Every pair of the tile is at least `gap` apart in time.
+                    const float gap = uniform(t_first - (sj[2 * (kTile - 1)].z + sj[2 * (kTile - 1) + 1].z));
+                    const bool no_b = gap >= rq.zero_gap_b, no_e = gap >= rq.zero_gap_e;
+                    far_mode = no_b ? (no_e ? kSkip : kFullLowE) : (no_e ? kFullLowB : kFullLow);
+                }
+                if (far_mode == kFullLow)
+                    sym_tile_fp32<kFullLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, tsh, tsl,
+                                                         nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+                else if (far_mode == kFullLowB)
+                    sym_tile_fp32<kFullLowB, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, tsh, tsl,
+                                                          nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+                else if (far_mode == kFullLowE)
+                    sym_tile_fp32<kFullLowE, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, tsh, tsl,
+                                                          nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+                else
+#pragma unroll
+                    for (int qq = 0; qq < KC; ++qq)
+#pragma unroll
+                        for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0f;
+            } else {
+                // Tiles that straddle the rows' causal counts or their own positions, and causal tiles
+                // closer in time to the rows than kNearTiles tile spans (taken by the masked path, whose
+                // masks then pass every pair): exact time differences, from the row times loaded here.
+                int ct[R];
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    ct[r] = rq.cut[lrow0 + r];
+                    if (GRAD) {  // short of registers: reloaded here rather than kept
+                        th[r] = rq.ev32[2 * (size_t)(lrow0 + r)].z;
+                        tl[r] = rq.ev32[2 * (size_t)(lrow0 + r) + 1].z;
+                    }
+                }
+                if (mode == kDiag)
+                    sym_tile_fp32<kDiag, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, tsh, tsl, nab,
+                                                      nae, kte, s, comp, colw, red_lds[wave], lane);
+                else
+                    sym_tile_fp32<kMaskLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, tsh, tsl,
+                                                         nab, nae, kte, s, comp, colw, red_lds[wave], lane);
+            }
+            __syncthreads();
+            // Column totals of this tile over the block's waves, in wave order (binary32: each is a
+            // sum of binary32 terms; the epilogue adds them over row blocks in binary64).
+            float* colpart32 = reinterpret_cast<float*>(rq.colpart);
+#pragma unroll
+            for (int c = threadIdx.x; c < kTile; c += NT) {
+                const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + c;
+#pragma unroll
+                for (int qq = 0; qq < KC; ++qq) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int w = 0; w < kSymWaves; ++w) v += (double)colred[w][qq][c];
+                    colpart32[qq * rq.col_stride + cb] = (float)v;
                 }
             }
-            if (mode == kDiag)
-                sym_tile_fp32<kDiag, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, tsh, tsl, nab,
-                                                  nae, kte, s, comp, colw, red_lds[wave], lane);
-            else
-                sym_tile_fp32<kMaskLow, GRAD, R, NT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, tsh, tsl,
-                                                     nab, nae, kte, s, comp, colw, red_lds[wave], lane);
-        }
-        __syncthreads();
-        // Column totals of this tile over the block's waves, in wave order (binary32: each is a
-        // sum of binary32 terms; the epilogue adds them over row blocks in binary64).
-        float* colpart32 = reinterpret_cast<float*>(rq.colpart);
-#pragma unroll
-        for (int c = threadIdx.x; c < kTile; c += NT) {
-            const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + c;
-#pragma unroll
-            for (int qq = 0; qq < KC; ++qq) {
-                double v = 0.0;
-#pragma unroll
-                for (int w = 0; w < kSymWaves; ++w) v += (double)colred[w][qq][c];
-                colpart32[qq * rq.col_stride + cb] = (float)v;
+            if (++kw == (ZSKIP ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
+                ++I;
+                kw = 0;
             }
         }
-        if (++kw == (ZSKIP ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
-            ++I;
-            kw = 0;
+        if (cur >= 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    rq.part[((size_t)(slot0 + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
+                        (double)s[k][r] + (double)comp[(k * R + r) * NT];
         }
-    }
-    if (cur >= 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k)
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] =
-                    (double)s[k][r] + (double)comp[(k * R + r) * NT];
+        // Next chunk of the dynamic tail (the counter starts at zero; every block stops at the first
+        // number beyond the last chunk).
+        if (ws.chunks == 0) break;
+        if (threadIdx.x == 0) next_chunk = (long long)atomicAdd(rq.ctr, 1ULL);
+        __syncthreads();
+        chunk = next_chunk;
+        __syncthreads();
+        if (chunk >= ws.chunks) break;
+        r0 = ws.sunits + split_begin(chunk, ws.cbase, ws.crem);
+        r1 = ws.sunits + split_begin(chunk + 1, ws.cbase, ws.crem);
+        slot0 = rq.items + rq.row_blocks + (int)chunk;
     }
 }
 
@@ -786,19 +816,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     __shared__ double colred[4][KC][kTile];
     __shared__ double red_lds[4][4 * 64];
 
+    __shared__ long long next_chunk;
     const int q = find_request(batch.r, batch.nreq, (int)blockIdx.x);
     const PairReq& rq = batch.r[q];
     const int blk = (int)blockIdx.x - rq.item_begin;
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int n = rq.n;
-    const SymWalk walk = sym_walk_begin(rq, blk);
-    long long u = walk.u;
-    const long long uend = walk.uend;
-    const long long ubeg = u;
+    // The walk of pair_sym_fp32c: the block's static range, then chunks of the dynamic tail.
+    const long long walk0 = ZSKIP ? 0 : rq.ubegin;
+    const WalkSplit ws = walk_split(ZSKIP ? rq.zcum[rq.row_blocks] : rq.units, rq.items, rq.dchunks);
+    long long r0 = split_begin(blk, ws.sbase, ws.srem), r1 = split_begin(blk + 1, ws.sbase, ws.srem);
+    const long long static_len = r1 - r0;
+    int slot0 = blk;  // row partials of row block I go to slot slot0 + I
     int prio = -1;
-    int I = walk.I;
-    int kw = walk.k;  // position of the current unit among row block I's walked tiles
 
     double x[R], y[R], t[R];
     int ct[R];
@@ -806,96 +837,127 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) v
     int cur = -1, w0 = 0, lrow0 = 0, clo = 0;
     bool active = false;
 
-    for (; u < uend; ++u) {
-        if (rq.balance) progress_priority(u - ubeg, uend - ubeg, prio);
-        if (I != cur) {
-            if (cur >= 0) {
-#pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    const int ka = GRAD ? k : (k == 0 ? 0 : 1);
-#pragma unroll
-                    for (int r = 0; r < R; ++r)
-                        rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] = a[ka][r];
-                }
-            }
-            cur = I;
-            w0 = I * kRowsPerBlock + wave * (64 * R);
-            lrow0 = w0 + R * lane;
-            active = w0 < n;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const double4 e = rq.ev64[lrow0 + r];
-                x[r] = e.x; y[r] = e.y; t[r] = e.z;
-                ct[r] = rq.cut[lrow0 + r];
-            }
-            clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
-#pragma unroll
-            for (int k = 0; k < 6; ++k)
-#pragma unroll
-                for (int r = 0; r < R; ++r) a[k][r] = 0.0;
-        }
-        const int tile = ZSKIP ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
-        const int j0 = tile * kTile;
-        __syncthreads();
-        sj[threadIdx.x] = rq.ev64[j0 + threadIdx.x];
-        __syncthreads();
-        int mode;
-        if (!active || j0 >= w0 + 64 * R) mode = kSkip;
-        else if (j0 + kTile <= w0) mode = (j0 + kTile <= clo) ? kFullLow : kMaskLow;
-        else mode = kDiag;
-        double* colw = &colred[wave][0][0];
-        if (mode == kSkip) {
-#pragma unroll
-            for (int qq = 0; qq < KC; ++qq)
-#pragma unroll
-                for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0;
-        } else if (mode == kFullLow) {
-            int far_mode = kFullLow;
+    for (long long chunk = -1;;) {
+        long long u = walk0 + r0;
+        const long long uend = walk0 + r1;
+        int I = 0, kw = 0;  // the current unit: the kw-th walked tile of row block I
+        if (u < uend) {
             if (ZSKIP) {
-                // Every pair of the tile is at least `gap` apart in time.
-                const double gap = uniform(rq.ev64[min(w0, n - 1)].z - sj[kTile - 1].z);
-                const bool no_b = gap >= (double)rq.zero_gap_b, no_e = gap >= (double)rq.zero_gap_e;
-                far_mode = no_b ? (no_e ? kSkip : kFullLowE) : (no_e ? kFullLowB : kFullLow);
+                I = zero_row_block(rq.zcum, rq.row_blocks, u);
+                kw = (int)(u - rq.zcum[I]);
+            } else {
+                I = sym_row_block(u);
+                kw = (int)(u - sym_unit0(I));
             }
-            if (far_mode == kFullLow)
-                sym_tile_fp64<kFullLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw,
-                                              red_lds[wave], lane);
-            else if (far_mode == kFullLowB)
-                sym_tile_fp64<kFullLowB, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw,
-                                               red_lds[wave], lane);
-            else if (far_mode == kFullLowE)
-                sym_tile_fp64<kFullLowE, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw,
-                                               red_lds[wave], lane);
-            else
+        }
+        cur = -1;
+        for (; u < uend; ++u) {
+            if (rq.balance) progress_priority(chunk < 0 ? u - walk0 - r0 : static_len, static_len, prio);
+            if (I != cur) {
+                if (cur >= 0) {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const int ka = GRAD ? k : (k == 0 ? 0 : 1);
+#pragma unroll
+                        for (int r = 0; r < R; ++r)
+                            rq.part[((size_t)(slot0 + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] = a[ka][r];
+                    }
+                }
+                cur = I;
+                w0 = I * kRowsPerBlock + wave * (64 * R);
+                lrow0 = w0 + R * lane;
+                active = w0 < n;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const double4 e = rq.ev64[lrow0 + r];
+                    x[r] = e.x; y[r] = e.y; t[r] = e.z;
+                    ct[r] = rq.cut[lrow0 + r];
+                }
+                clo = __builtin_amdgcn_readfirstlane(rq.cut[min(w0, n - 1)]);
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+#pragma unroll
+                    for (int r = 0; r < R; ++r) a[k][r] = 0.0;
+            }
+            const int tile = ZSKIP ? walk_tile(rq.zcum, rq.row_blocks, I, kw) : kw;
+            const int j0 = tile * kTile;
+            __syncthreads();
+            sj[threadIdx.x] = rq.ev64[j0 + threadIdx.x];
+            __syncthreads();
+            int mode;
+            if (!active || j0 >= w0 + 64 * R) mode = kSkip;
+            else if (j0 + kTile <= w0) mode = (j0 + kTile <= clo) ? kFullLow : kMaskLow;
+            else mode = kDiag;
+            double* colw = &colred[wave][0][0];
+            if (mode == kSkip) {
 #pragma unroll
                 for (int qq = 0; qq < KC; ++qq)
 #pragma unroll
                     for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0;
-        } else if (mode == kMaskLow) {
-            sym_tile_fp64<kMaskLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, red_lds[wave], lane);
-        } else {
-            sym_tile_fp64<kDiag, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, red_lds[wave], lane);
+            } else if (mode == kFullLow) {
+                int far_mode = kFullLow;
+                if (ZSKIP) {
+                    // Every pair of the tile is at least `gap` apart in time.
+                    const double gap = uniform(rq.ev64[min(w0, n - 1)].z - sj[kTile - 1].z);
+                    const bool no_b = gap >= (double)rq.zero_gap_b, no_e = gap >= (double)rq.zero_gap_e;
+                    far_mode = no_b ? (no_e ? kSkip : kFullLowE) : (no_e ? kFullLowB : kFullLow);
+                }
+                if (far_mode == kFullLow)
+                    sym_tile_fp64<kFullLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw,
+                                                  red_lds[wave], lane);
+                else if (far_mode == kFullLowB)
+                    sym_tile_fp64<kFullLowB, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw,
+                                                   red_lds[wave], lane);
+                else if (far_mode == kFullLowE)
+                    sym_tile_fp64<kFullLowE, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw,
+                                                   red_lds[wave], lane);
+                else
+#pragma unroll
+                    for (int qq = 0; qq < KC; ++qq)
+#pragma unroll
+                        for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0;
+            } else if (mode == kMaskLow) {
+                sym_tile_fp64<kMaskLow, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, red_lds[wave], lane);
+            } else {
+                sym_tile_fp64<kDiag, GRAD>(sj, j0, lrow0, x, y, t, ct, rq.nab64, rq.nbb64, rq.nae64, rq.nbe64, a, colw, red_lds[wave], lane);
+            }
+            __syncthreads();
+            const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;
+#pragma unroll
+            for (int qq = 0; qq < KC; ++qq)
+                rq.colpart[qq * rq.col_stride + cb] = colred[0][qq][threadIdx.x] + colred[1][qq][threadIdx.x] +
+                                                      colred[2][qq][threadIdx.x] + colred[3][qq][threadIdx.x];
+            if (++kw == (ZSKIP ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
+                ++I;
+                kw = 0;
+            }
         }
+        if (cur >= 0) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int ka = GRAD ? k : (k == 0 ? 0 : 1);
+#pragma unroll
+                for (int r = 0; r < R; ++r)
+                    rq.part[((size_t)(slot0 + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] = a[ka][r];
+            }
+        }
+        if (ws.chunks == 0) break;
+        if (threadIdx.x == 0) next_chunk = (long long)atomicAdd(rq.ctr, 1ULL);
         __syncthreads();
-        const long long cb = (long long)kRowsPerBlock * I * (I + 1) / 2 + j0 + threadIdx.x;
-#pragma unroll
-        for (int qq = 0; qq < KC; ++qq)
-            rq.colpart[qq * rq.col_stride + cb] = colred[0][qq][threadIdx.x] + colred[1][qq][threadIdx.x] +
-                                                  colred[2][qq][threadIdx.x] + colred[3][qq][threadIdx.x];
-        if (++kw == (ZSKIP ? walk_units(rq.zcum, rq.row_blocks, I) : TB * (I + 1))) {
-            ++I;
-            kw = 0;
-        }
+        chunk = next_chunk;
+        __syncthreads();
+        if (chunk >= ws.chunks) break;
+        r0 = ws.sunits + split_begin(chunk, ws.cbase, ws.crem);
+        r1 = ws.sunits + split_begin(chunk + 1, ws.cbase, ws.crem);
+        slot0 = rq.items + rq.row_blocks + (int)chunk;
     }
-    if (cur >= 0) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int ka = GRAD ? k : (k == 0 ? 0 : 1);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                rq.part[((size_t)(blk + cur) * K + k) * kRowsPerBlock + wave * 64 * R + R * lane + r] = a[ka][r];
-        }
-    }
+}
+
+// Zero the dynamic-tail counters of the launch's requests (before their symmetric pass).
+__global__ __launch_bounds__(64) void walk_reset(const PairBatch batch)
+{
+    const int k = threadIdx.x;
+    if (k < batch.nreq && batch.r[k].dchunks > 0) *batch.r[k].ctr = 0ULL;
 }
 
 }  // namespace
@@ -912,6 +974,13 @@ hipError_t launch_pair(const PairBatch& b, int precision, bool grad, int scheme,
     if (b.total_items <= 0) return hipSuccess;
     const dim3 grid(b.total_items), block(kThreads);
     if (scheme == kSymmetric) {
+        bool dynamic_tail = false;
+        for (int k = 0; k < b.nreq; ++k) dynamic_tail = dynamic_tail || b.r[k].dchunks > 0;
+        if (dynamic_tail) {
+            walk_reset<<<dim3(1), dim3(64), 0, s>>>(b);
+            const hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
         if (precision == kFP32C) {
             if (zskip) {
                 if (grad) pair_sym_fp32c<true, true><<<grid, dim3(kSymThreads), 0, s>>>(b);

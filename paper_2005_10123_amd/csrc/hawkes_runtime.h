@@ -42,6 +42,7 @@ struct Plan {
     long long units = 0;      // symmetric: (row block, column tile) units this evaluation walks
     long long ubegin = 0;     // symmetric: first of them in the row-major order of the lower triangle
     long long col_stride = 0; // symmetric: values per column-sum quantity
+    int dchunks = 0;          // symmetric: chunks of the walk's dynamic tail (dev::walk_split)
     size_t part_doubles = 0;  // row partial sums
     size_t col_bytes = 0;     // symmetric: column partial sums (binary32 values for FP32C, binary64
                               // for FP64), rounded up to a multiple of 8 bytes
@@ -54,6 +55,8 @@ struct Plan {
 struct Carved {
     double *part = nullptr, *colpart = nullptr, *block_part = nullptr, *out7 = nullptr, *rows = nullptr;
     long long* zcum = nullptr;  // zero-tile skipping tables, when the plan uses them
+    unsigned long long* ctr = nullptr;  // the dynamic tail's chunk counter (the 8th double of the
+                                        // scratch's result slot, which holds 7 results)
 };
 
 struct Scratch {

@@ -73,7 +73,12 @@ Plan make_plan(const hawkes_ctx* c, int64_t n, int npad, bool grad, int precisio
         pl.items = (int)std::min(slots, pl.units);
         pl.ubase = pl.items > 0 ? (int)(pl.units / pl.items) : 1;
         pl.urem = pl.items > 0 ? (int)(pl.units % pl.items) : 0;
-        pl.part_doubles = (size_t)(pl.items + T) * pl.K * kRowsPerBlock;
+        // Dynamic tail (walk_split): up to kDynChunksPerBlock chunks per block, each with row
+        // partial slots of its own.
+        pl.dchunks = pl.units >= kDynMinUnitsPerBlock * pl.items
+                         ? (int)std::min<long long>(pl.units / kDynDiv, (long long)kDynChunksPerBlock * pl.items)
+                         : 0;
+        pl.part_doubles = (size_t)(pl.items + T + (pl.dchunks > 0 ? pl.dchunks + T : 0)) * pl.K * kRowsPerBlock;
         pl.col_stride = (long long)kRowsPerBlock * T * (T + 1) / 2;
         // The FP32C pass writes binary32 column partials (sums of binary32 terms over one row
         // block), the FP64 pass binary64 ones.
@@ -150,6 +155,7 @@ void fill_epi(const hawkes_params& p, const Dataset& d, const Plan& pl, bool gra
     e.add_diag = 1;
     e.nblocks = pl.epi_blocks;
     e.pair_items = pl.items;
+    e.dchunks = pl.dchunks;
     e.zcum = cv.zcum;
     e.T = d.T;
     e.mu0 = p.mu0;
@@ -211,6 +217,8 @@ void fill_pair(const hawkes_params& p, const Dataset& d, const Plan& pl, const C
     r.urem = pl.urem;
     r.ubegin = pl.ubegin;
     r.items = pl.items;
+    r.dchunks = pl.dchunks;
+    r.ctr = cv.ctr;
     r.zcum = cv.zcum;
     r.zdirect = pl.zdirect ? 1 : 0;
     double gap_b, gap_e;
@@ -302,6 +310,7 @@ Carved carve(char* base, const Plan& pl, bool rows)
     cv.block_part = p;
     p += (size_t)pl.epi_blocks * 7;
     cv.out7 = p;
+    cv.ctr = (unsigned long long*)(p + 7);
     p += 8;
     cv.zcum = pl.zskip ? (long long*)p : nullptr;
     p += pl.zbytes / sizeof(double);
