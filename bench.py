@@ -493,7 +493,7 @@ def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed
     think = max(chains * mean_service / utilisation - mean_service, 0.0)
     next_t = time.perf_counter() + rng.exponential(think, chains)
     waiting = np.ones(chains, dtype=bool)
-    lat, pairs, tag_chain = [], 0.0, {}
+    lat, lat_ds, pairs, tag_chain = [], [], 0.0, {}
     tag = 0
     t_start = time.perf_counter()
     t_measure = t_start + warmup
@@ -519,6 +519,7 @@ def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed
                 raise RuntimeError(f"request failed with status {r.status}")
             if measured:
                 lat.append((r.t_done_ns - r.t_submit_ns) * 1e-9)
+                lat_ds.append(k % datasets)
                 pairs += float(sizes[k % datasets]) ** 2
                 t_last = time.perf_counter()
             waiting[k] = True
@@ -526,12 +527,18 @@ def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed
     wall = t_last - t_measure
     for ds in dss:
         ds.close()
-    lat = np.array(lat)
+    lat, lat_ds = np.array(lat), np.array(lat_ds)
+    by_size = []
+    for d in np.argsort(sizes):
+        ld = lat[lat_ds == d]
+        if ld.size:
+            by_size.append({"n": int(sizes[d]), "solo_ms": cost[d] * 1e3, "requests": int(ld.size),
+                            "p50_ms": float(np.percentile(ld, 50) * 1e3), "p99_ms": float(np.percentile(ld, 99) * 1e3)})
     return {"requests": int(lat.size), "chains": chains, "datasets": datasets, "offered_utilisation": utilisation,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p90_ms": float(np.percentile(lat, 90) * 1e3),
             "p99_ms": float(np.percentile(lat, 99) * 1e3),
             "pairs_per_s": pairs / wall, "seconds": wall, "warmup_seconds": warmup,
-            "sizes": [int(s) for s in sizes]}
+            "sizes": [int(s) for s in sizes], "largest_solo_ms": max(cost) * 1e3, "by_dataset": by_size}
 
 
 def pi_batch_run(ctx, n=55000, samples=64, seed=7):
