@@ -468,8 +468,9 @@ def shard_run(ctx, nshards=8, workload="stress_1m"):
 
 
 def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed=4, warmup=1.0,
-                min_requests=10000, max_seconds=20.0):
-    """Closed-loop chains with Poisson think times over 16 resident datasets of log-uniform size.
+                min_requests=10000, max_seconds=20.0, grad=True):
+    """Closed-loop chains with Poisson think times over 16 resident datasets of log-uniform size,
+    FP32C requests with the gradient (grad) or log-likelihood only.
     Latencies count from the requests submitted after `warmup` seconds; submission goes on for at
     least `seconds` and until `min_requests` have been measured (at most `max_seconds`)."""
     from paper_2005_10123_amd import binding, synth
@@ -483,10 +484,11 @@ def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed
     rng = np.random.default_rng(seed)
     # Capacity estimate from one blocking evaluation per dataset.
     cost = []
+    evaluate = ctx.grad if grad else ctx.loglik
     for ds in dss:
-        ctx.grad(ds, theta0, "fp32c")
+        evaluate(ds, theta0, "fp32c")
         a = time.perf_counter()
-        ctx.grad(ds, theta0, "fp32c")
+        evaluate(ds, theta0, "fp32c")
         cost.append(time.perf_counter() - a)
     mean_service = float(np.mean([cost[k % datasets] for k in range(chains)]))
     # Offered load: chains / (think + service) requests per second = utilisation / mean_service.
@@ -508,7 +510,7 @@ def serving_run(ctx, seconds=8.0, chains=256, datasets=16, utilisation=0.8, seed
             reqs = []
             for k in due:
                 th = theta0 * np.exp(0.1 * rng.standard_normal(6))
-                reqs.append(binding.request(dss[k % datasets], th, "fp32c", True, tag))
+                reqs.append(binding.request(dss[k % datasets], th, "fp32c", grad, tag))
                 tag_chain[tag] = (k, now >= t_measure)
                 tag += 1
                 waiting[k] = False
@@ -622,6 +624,16 @@ def mcmc_run(ctx, chains=4, steps=2000, hmc_iterations=300, hmc_warmup=100, seed
                "step_size": [c.eps for c in hch], "ess": ess_report(mcmc.chain_ess(hch, 0.0), sec)}
         out["zero_tile_skip" if skip else "all_pairs"] = {"mh": mh, "hmc": hmc}
     ctx.set_zero_tile_skipping(False)
+    # The MH chains' log-likelihood requests in shared multi-parameter passes (off by default).
+    ctx.set_shared_passes(True)
+    chs = [mcmc.ChainState(np.array(theta0, float), np.random.default_rng(seed + k)) for k in range(chains)]
+    a = time.perf_counter()
+    served = mcmc.run_served(ctx, chs, [ds] * chains, steps)
+    sec = time.perf_counter() - a
+    ctx.set_shared_passes(False)
+    out["all_pairs_shared_passes"] = {"mh": {"seconds": sec, "evaluations": served, "evaluations_per_s": served / sec,
+                                             "acceptance": float(np.mean([c.accepted / max(c.steps, 1) for c in chs]))}}
+    out["shared_pass_speedup_mh"] = (served / sec) / out["all_pairs"]["mh"]["evaluations_per_s"]
     ds.close()
     return out
 
@@ -806,6 +818,17 @@ def main():
         result["serving_zero_tile_skip"] = {k: r[k] for k in ("offered_utilisation", "requests", "p50_ms", "p90_ms",
                                                                "p99_ms", "pairs_per_s")}
         result["serving_chains"] = leg("serving_chains", chain_serving_run, ctx)
+        # Log-likelihood-only load (the requests of Algorithm 1's chains) with the scheduler's shared
+        # multi-parameter passes and without them, saturated (offered load 2.0) and at 0.8.
+        result["serving_loglik"] = {}
+        for shared in (True, False):
+            ctx.set_shared_passes(shared)
+            for u in (0.8, 2.0):
+                r = leg(f"serving_loglik shared={shared} {u}", serving_run, ctx, seconds=3.0, utilisation=u,
+                        min_requests=0, grad=False)
+                result["serving_loglik"][f"{'shared' if shared else 'unshared'}_{u}"] = {
+                    k: r[k] for k in ("offered_utilisation", "requests", "p50_ms", "p99_ms", "pairs_per_s")}
+        ctx.set_shared_passes(False)
         result["pi_batch"] = leg("pi_batch", pi_batch_run, ctx)
         result["mcmc"] = leg("mcmc", mcmc_run, ctx)
     ctx.close()

@@ -229,6 +229,21 @@ hawkes_status hawkes_set_pair_scheme(hawkes_ctx* ctx, int scheme);
  * hawkes_shard_sums. */
 hawkes_status hawkes_set_zero_tile_skipping(hawkes_ctx* ctx, int enable);
 
+/* Shared passes for served log-likelihoods (enable: 1, or 0, the default).  Chains of the paper's
+ * sampler (Algorithm 1, step 5a) each ask for one log-likelihood per proposal, many of them on the
+ * same dataset.  With shared passes on, submitted HAWKES_FP32C requests without the gradient are
+ * evaluated by the multi-parameter pass of hawkes_loglik_multi: the requests of one launch on one
+ * dataset share passes of up to 4 parameter vectors, each pair's differences formed once for all
+ * of them.  A request's result is then bitwise hawkes_loglik_multi's value for its vector, the
+ * same alone or grouped (which vectors share a pass does not change any vector's arithmetic), and
+ * agrees with hawkes_loglik to rounding (a different grouping of the same binary32 terms).  With
+ * zero-tile skipping on, each such request has a pass of its own (the tiles a pass leaves out
+ * depend on all of its vectors).  With shared passes off, those requests are evaluated like
+ * hawkes_loglik, bitwise.  Applies to requests admitted after the call.  Off by default: a request
+ * that finds no companions has a pass of one vector, which costs more than the single-parameter
+ * pass, and on MI355X the sharing gained little where groups formed. */
+hawkes_status hawkes_set_shared_passes(hawkes_ctx* ctx, int enable);
+
 /* ---- host evaluation ------------------------------------------------------------------------
  * The paper's multi-core CPU design (Section 2.3; its CPU algorithms for the log-likelihood and the
  * self-excitation probabilities): the events' rows are dealt to `threads` host threads, each

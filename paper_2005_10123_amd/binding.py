@@ -104,6 +104,7 @@ def load(path: str | None = None):
         "hawkes_profile": ([vp, ctypes.c_int], i32),
         "hawkes_set_pair_scheme": ([vp, ctypes.c_int], i32),
         "hawkes_set_zero_tile_skipping": ([vp, ctypes.c_int], i32),
+        "hawkes_set_shared_passes": ([vp, ctypes.c_int], i32),
         "hawkes_loglik_multi": ([vp, i32, ctypes.POINTER(Params), i32, ctypes.c_int, _dp, _dp], i32),
         "hawkes_kernel_time": ([vp, _dp, ctypes.POINTER(i64), ctypes.c_int], i32),
         "hawkes_host_eval": ([_dp, _dp, _dp, i64, ctypes.POINTER(Params), ctypes.c_int, _dp, _dp], i32),
@@ -278,6 +279,10 @@ class Context:
     def set_zero_tile_skipping(self, enable=True):
         """Leave out the column tiles whose pair terms are all exactly zero (see include/hawkes.h)."""
         _check(self.lib.hawkes_set_zero_tile_skipping(self._h, 1 if enable else 0))
+
+    def set_shared_passes(self, enable=True):
+        """Served FP32C log-likelihoods in shared multi-parameter passes (see include/hawkes.h)."""
+        _check(self.lib.hawkes_set_shared_passes(self._h, 1 if enable else 0))
 
     # -- diagnostics ---------------------------------------------------------------------------
     def profile(self, enable=True):

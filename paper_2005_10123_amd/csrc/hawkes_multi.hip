@@ -17,7 +17,6 @@
 
 namespace hawkes {
 
-constexpr int kMultiTheta = 4;
 // Shape of the FP32C multi-parameter pass: kMultiRows rows per lane; a block's threads together hold
 // one row block of the walk; the register budget is sized for kMultiWavesPerSimd waves per SIMD.
 constexpr int kMultiRows = 4;
@@ -45,7 +44,8 @@ struct MultiEpi {
     int items;              // blocks of the pairwise pass
     double* pi_out;      // [nth][n] in sorted order, or nullptr
     double* block_part;  // [nblocks][kMultiTheta]
-    double* out;         // kMultiTheta log-likelihoods
+    double* out;         // log-likelihood of vector q at out[q * out_stride]
+    int out_stride;
     long long col_stride;
     int n, npad, row_blocks, ubase, urem, nth, nblocks;
     double T;
@@ -57,20 +57,19 @@ namespace {
 
 using namespace dev;
 
-template <int MODE>
+template <int MODE, int KT>
 __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0, int lrow0,
                                            const float (&xh)[kMultiRows], const float (&yh)[kMultiRows],
                                            const float (&xl)[kMultiRows], const float (&yl)[kMultiRows],
                                            const float (&ti)[kMultiRows], const float (&th)[kMultiRows],
                                            const float (&tl)[kMultiRows], const int (&ct)[kMultiRows],
-                                           float t0h, float t0l, const float (&nab)[kMultiTheta],
-                                           const float (&nbb)[kMultiTheta], const float (&nae)[kMultiTheta],
-                                           const float (&nbe)[kMultiTheta], float (&s)[2 * kMultiTheta][kMultiRows],
+                                           float t0h, float t0l, const float (&nab)[KT],
+                                           const float (&nbb)[KT], const float (&nae)[KT],
+                                           const float (&nbe)[KT], float (&s)[2 * KT][kMultiRows],
                                            volatile lds_float* comp, float* __restrict__ colw,
                                            float* __restrict__ red, int lane)
 {
     constexpr int R = kMultiRows;
-    constexpr int KT = kMultiTheta;
     // Far tiles measure times from the lane's first row; masked and near ones take each pair's time
     // difference from the hi/lo parts of both events (see kNearSpans).
     constexpr bool EXACT = MODE != kFullLow;
@@ -132,10 +131,12 @@ __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0
     }
 }
 
+// KT parameter vectors per pass (1 to kMultiTheta); a vector's arithmetic is the same for every KT,
+// so its results do not depend on the vectors it shares a pass with.
+template <int KT>
 __global__ __launch_bounds__(kMultiThreads) __attribute__((amdgpu_waves_per_eu(kMultiWavesPerSimd))) void pair_multi_fp32c(const MultiReq rq)
 {
     constexpr int R = kMultiRows;
-    constexpr int KT = kMultiTheta;
     constexpr int K = 2 * KT;
     constexpr int TB = kRowsPerBlock / kTile;
     __shared__ float4 sj[2 * kTile];
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(kMultiThreads) __attribute__((amdgpu_waves_per_eu(k
             for (int r = 0; r < R; ++r)
                 ti[r] = (rq.ev32[2 * (size_t)(lrow0 + r)].z - t0h) + (rq.ev32[2 * (size_t)(lrow0 + r) + 1].z - t0l);
             const int ct[R] = {};  // not read: every column of the tile is causal for every row
-            multi_tile<kFullLow>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw,
+            multi_tile<kFullLow, KT>(sj, j0, lrow0, xh, yh, xl, yl, ti, ti, ti, ct, t0h, t0l, nab, nbb, nae, nbe, s, comp, colw,
                                  red_lds[wave], lane);
         } else {
             // Straddling tiles and near causal ones (the masked path; its causal mask then passes
@@ -251,10 +252,10 @@ __global__ __launch_bounds__(kMultiThreads) __attribute__((amdgpu_waves_per_eu(k
                 tl[r] = rq.ev32[2 * (size_t)(lrow0 + r) + 1].z;
             }
             if (mode == kDiag)
-                multi_tile<kDiag>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, nab, nbb, nae, nbe, s, comp, colw,
+                multi_tile<kDiag, KT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, nab, nbb, nae, nbe, s, comp, colw,
                                   red_lds[wave], lane);
             else
-                multi_tile<kMaskLow>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, nab, nbb, nae, nbe, s, comp,
+                multi_tile<kMaskLow, KT>(sj, j0, lrow0, xh, yh, xl, yl, th, th, tl, ct, 0.0f, 0.0f, nab, nbb, nae, nbe, s, comp,
                                      colw, red_lds[wave], lane);
         }
         __syncthreads();
@@ -286,9 +287,9 @@ __global__ __launch_bounds__(kMultiThreads) __attribute__((amdgpu_waves_per_eu(k
 __device__ __forceinline__ double normal_cdf(double z) { return 0.5 * erfc(-z * 0.70710678118654752440); }
 
 // Per event and parameter vector: lambda, Lambda, ell_i and pi_i (binary64); block sums of ell.
+template <int KT>
 __global__ __launch_bounds__(kThreads) void epilogue_multi(const MultiEpi e)
 {
-    constexpr int KT = kMultiTheta;
     constexpr long long TB = kRowsPerBlock / kTile;
     __shared__ double red[KT][kThreads];
     const int i = blockIdx.x * kThreads + threadIdx.x;
@@ -356,9 +357,9 @@ __global__ __launch_bounds__(kThreads) void epilogue_multi(const MultiEpi e)
         for (int q = 0; q < KT; ++q) e.block_part[(size_t)blockIdx.x * KT + q] = red[q][0];
 }
 
+template <int KT>
 __global__ __launch_bounds__(kThreads) void final_multi(const MultiEpi e)
 {
-    constexpr int KT = kMultiTheta;
     __shared__ double red[KT][kThreads];
     double v[KT] = {};
     for (int b = threadIdx.x; b < e.nblocks; b += kThreads)
@@ -375,7 +376,7 @@ __global__ __launch_bounds__(kThreads) void final_multi(const MultiEpi e)
     }
     if (threadIdx.x == 0)
 #pragma unroll
-        for (int q = 0; q < KT; ++q) e.out[q] = red[q][0];
+        for (int q = 0; q < KT; ++q) e.out[(size_t)q * e.out_stride] = red[q][0];
 }
 
 }  // namespace
@@ -383,107 +384,157 @@ __global__ __launch_bounds__(kThreads) void final_multi(const MultiEpi e)
 int multi_blocks_per_cu()
 {
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_multi_fp32c, kMultiThreads, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pair_multi_fp32c<kMultiTheta>, kMultiThreads, 0);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-// FP32C: kMultiTheta parameter vectors per pass.  Caller holds c->mu.
-static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_params* th, int S, double* out_ll,
-                                 double* out_pi)
+// Split and scratch layout of the FP32C multi-parameter pass over one dataset.  They do not depend
+// on the number of vectors in a pass (the grid is sized for kMultiTheta), so a vector's result is the
+// same whichever vectors share its pass.
+struct MultiPlan {
+    long long T = 0, units = 0, col_stride = 0;
+    int items = 0, ubase = 0, urem = 0, nblocks = 0;
+    size_t part_d = 0, col_d = 0, z_d = 0;  // doubles
+};
+
+static MultiPlan multi_plan(const hawkes_ctx* c, const Dataset& d, bool zero_skip)
 {
     constexpr int KT = kMultiTheta;
     const long long TB = kRowsPerBlock / kTile;
-    const long long T = d.npad / kRowsPerBlock;
-    const long long units = TB * T * (T + 1) / 2;
+    MultiPlan m;
+    m.T = d.npad / kRowsPerBlock;
+    m.units = TB * m.T * (m.T + 1) / 2;
     const long long slots = std::max(1, c->multi_slots);
-    const int items = (int)std::min(slots, units);
-    const int ubase = (int)(units / items), urem = (int)(units % items);
-    const long long col_stride = (long long)kRowsPerBlock * T * (T + 1) / 2;
-    const int nblocks = (int)((d.n + kThreads - 1) / kThreads);
-    const size_t part_d = (size_t)(items + T) * 2 * KT * kRowsPerBlock;
-    const size_t col_d = (size_t)KT * col_stride;
-    const size_t pi_d = out_pi ? (size_t)KT * d.n : 0;
-    const bool zero_skip = c->zero_skip;
-    const size_t z_d = zero_skip ? ((size_t)(T + 1) * sizeof(long long) + (size_t)T * sizeof(int) + 7) / 8 : 0;
-    const size_t need = (part_d + col_d + (size_t)nblocks * KT + 8 + pi_d + z_d) * sizeof(double);
-    hawkes_status st = reserve_blocking(c, need);
-    if (st != HAWKES_OK) return st;
-    double* base = (double*)c->blk.base;
+    m.items = (int)std::min(slots, m.units);
+    m.ubase = (int)(m.units / m.items);
+    m.urem = (int)(m.units % m.items);
+    m.col_stride = (long long)kRowsPerBlock * m.T * (m.T + 1) / 2;
+    m.nblocks = (int)((d.n + kThreads - 1) / kThreads);
+    m.part_d = (size_t)(m.items + m.T) * 2 * KT * kRowsPerBlock;
+    m.col_d = (size_t)KT * m.col_stride;
+    m.z_d = zero_skip ? ((size_t)(m.T + 1) * sizeof(long long) + (size_t)m.T * sizeof(int) + 7) / 8 : 0;
+    return m;
+}
+
+// Scratch of one pass: row partials, column partials, block partials, 8 result doubles, zero-tile
+// tables, then (want_pi) kMultiTheta x n probabilities.
+size_t multi_scratch_bytes(const hawkes_ctx* c, const Dataset& d, bool zero_skip, bool want_pi)
+{
+    const MultiPlan m = multi_plan(c, d, zero_skip);
+    const size_t pi_d = want_pi ? (size_t)kMultiTheta * d.n : 0;
+    return (m.part_d + m.col_d + (size_t)m.nblocks * kMultiTheta + 8 + m.z_d + pi_d) * sizeof(double);
+}
+
+template <int KT>
+static hipError_t launch_multi(const MultiReq& r, const MultiEpi& e, int items, int nblocks, hipStream_t s)
+{
+    pair_multi_fp32c<KT><<<dim3(items), dim3(kMultiThreads), 0, s>>>(r);
+    epilogue_multi<KT><<<dim3(nblocks), dim3(kThreads), 0, s>>>(e);
+    final_multi<KT><<<dim3(1), dim3(kThreads), 0, s>>>(e);
+    return hipGetLastError();
+}
+
+// Enqueue one pass over nth (1 to kMultiTheta) parameter vectors on stream s: ell of vector q to
+// out[q * out_stride] (device memory), pi of event i (sorted order) to pi_out[q * n + i] when pi_out
+// is set.  The scratch is laid out as multi_scratch_bytes describes.
+hipError_t enqueue_multi_fp32c(const hawkes_ctx* c, const Dataset& d, const hawkes_params* th, int nth, char* scratch,
+                               bool zero_skip, double* out, int out_stride, double* pi_out, hipStream_t s)
+{
+    constexpr int KT = kMultiTheta;
+    const MultiPlan m = multi_plan(c, d, zero_skip);
+    double* base = (double*)scratch;
     MultiReq r;
     memset(&r, 0, sizeof r);
     r.ev32 = d.ev32;
     r.cut = d.cut;
     r.part = base;
-    r.colpart = base + part_d;
-    r.units = units;
-    r.col_stride = col_stride;
+    r.colpart = base + m.part_d;
+    r.units = m.units;
+    r.col_stride = m.col_stride;
     r.n = (int)d.n;
     r.npad = d.npad;
-    r.row_blocks = (int)T;
-    r.ubase = ubase;
-    r.urem = urem;
-    r.items = items;
+    r.row_blocks = (int)m.T;
+    r.ubase = m.ubase;
+    r.urem = m.urem;
+    r.items = m.items;
     MultiEpi e;
     memset(&e, 0, sizeof e);
     e.ev64 = d.ev64;
     e.part = r.part;
     e.colpart = r.colpart;
-    e.block_part = base + part_d + col_d;
-    e.out = e.block_part + (size_t)nblocks * KT;
-    e.pi_out = out_pi ? e.out + 8 : nullptr;
-    r.zcum = zero_skip ? (long long*)(e.out + 8 + pi_d) : nullptr;
+    e.block_part = base + m.part_d + m.col_d;
+    e.out = out;
+    e.out_stride = out_stride;
+    e.pi_out = pi_out;
+    r.zcum = zero_skip ? (long long*)(e.block_part + (size_t)m.nblocks * KT + 8) : nullptr;
     e.zcum = r.zcum;
-    e.items = items;
-    // Zero-tile tables of each pass: the tiles where the pair terms of all its vectors vanish.
-    PairBatch zb;
-    memset(&zb, 0, sizeof zb);
-    zb.nreq = 1;
-    zb.r[0].ev64 = d.ev64;
-    zb.r[0].row_blocks = (int)T;
-    zb.r[0].zcum = r.zcum;
-    e.col_stride = col_stride;
+    e.items = m.items;
+    e.col_stride = m.col_stride;
     e.n = (int)d.n;
     e.npad = d.npad;
-    e.row_blocks = (int)T;
-    e.ubase = ubase;
-    e.urem = urem;
-    e.nblocks = nblocks;
+    e.row_blocks = (int)m.T;
+    e.ubase = m.ubase;
+    e.urem = m.urem;
+    e.nblocks = m.nblocks;
     e.T = d.T;
+    e.nth = nth;
     const double log2e = 1.44269504088896340736, two_pi = 6.28318530717958647693;
+    for (int q = 0; q < nth; ++q) {
+        const hawkes_params& p = th[q];
+        r.nab[q] = (float)(-log2e / (2.0 * p.tau_x * p.tau_x));
+        r.nbb[q] = (float)(-log2e / (2.0 * p.tau_t * p.tau_t));
+        r.nae[q] = (float)(-log2e / (2.0 * p.h * p.h));
+        r.nbe[q] = (float)(-log2e * p.omega);
+        e.mu0[q] = p.mu0;
+        e.tau_t[q] = p.tau_t;
+        e.theta[q] = p.theta;
+        e.omega[q] = p.omega;
+        e.cb[q] = p.mu0 / (std::pow(two_pi, 1.5) * p.tau_x * p.tau_x * p.tau_t);
+        e.ce[q] = p.theta * p.omega / (two_pi * p.h * p.h);
+    }
+    hipError_t err = hipSuccess;
+    if (zero_skip) {
+        // Zero-tile tables of the pass: the tiles where the pair terms of all its vectors vanish.
+        PairBatch zb;
+        memset(&zb, 0, sizeof zb);
+        zb.nreq = 1;
+        zb.r[0].ev64 = d.ev64;
+        zb.r[0].row_blocks = (int)m.T;
+        zb.r[0].zcum = r.zcum;
+        double zdt = 0.0;
+        for (int q = 0; q < nth; ++q) zdt = std::max(zdt, zero_separation(th[q], kFP32C, d.T));
+        zb.r[0].zero_dt = zdt;
+        if ((err = launch_zero_prefix(zb, s)) != hipSuccess) return err;
+    }
+    switch (nth) {
+    case 1: return launch_multi<1>(r, e, m.items, m.nblocks, s);
+    case 2: return launch_multi<2>(r, e, m.items, m.nblocks, s);
+    case 3: return launch_multi<3>(r, e, m.items, m.nblocks, s);
+    default: return launch_multi<4>(r, e, m.items, m.nblocks, s);
+    }
+}
+
+// FP32C: up to kMultiTheta parameter vectors per pass.  Caller holds c->mu.
+static hawkes_status multi_fp32c(hawkes_ctx* c, const Dataset& d, const hawkes_params* th, int S, double* out_ll,
+                                 double* out_pi)
+{
+    constexpr int KT = kMultiTheta;
+    const bool zero_skip = c->zero_skip;
+    const MultiPlan m = multi_plan(c, d, zero_skip);
+    hawkes_status st = reserve_blocking(c, multi_scratch_bytes(c, d, zero_skip, out_pi != nullptr));
+    if (st != HAWKES_OK) return st;
+    double* out = (double*)c->blk.base + m.part_d + m.col_d + (size_t)m.nblocks * KT;
+    double* pi_dev = out_pi ? out + 8 + m.z_d : nullptr;
     std::vector<double> host_out(8);
     std::vector<double> host_pi(out_pi ? (size_t)KT * d.n : 0);
     hipStream_t s = c->stream;
     hipError_t err = hipStreamWaitEvent(s, c->blk_free, 0);
     for (int s0 = 0; s0 < S && err == hipSuccess; s0 += KT) {
         const int nth = std::min(KT, S - s0);
-        e.nth = nth;
-        for (int q = 0; q < KT; ++q) {
-            const hawkes_params& p = th[s0 + std::min(q, nth - 1)];  // pad with the last vector
-            r.nab[q] = (float)(-log2e / (2.0 * p.tau_x * p.tau_x));
-            r.nbb[q] = (float)(-log2e / (2.0 * p.tau_t * p.tau_t));
-            r.nae[q] = (float)(-log2e / (2.0 * p.h * p.h));
-            r.nbe[q] = (float)(-log2e * p.omega);
-            e.mu0[q] = p.mu0;
-            e.tau_t[q] = p.tau_t;
-            e.theta[q] = p.theta;
-            e.omega[q] = p.omega;
-            e.cb[q] = p.mu0 / (std::pow(two_pi, 1.5) * p.tau_x * p.tau_x * p.tau_t);
-            e.ce[q] = p.theta * p.omega / (two_pi * p.h * p.h);
-        }
-        if (zero_skip) {
-            double zdt = 0.0;
-            for (int q = 0; q < nth; ++q) zdt = std::max(zdt, zero_separation(th[s0 + q], kFP32C, d.T));
-            zb.r[0].zero_dt = zdt;
-            err = launch_zero_prefix(zb, s);
-            if (err != hipSuccess) break;
-        }
-        pair_multi_fp32c<<<dim3(items), dim3(kMultiThreads), 0, s>>>(r);
-        epilogue_multi<<<dim3(nblocks), dim3(kThreads), 0, s>>>(e);
-        final_multi<<<dim3(1), dim3(kThreads), 0, s>>>(e);
-        err = hipGetLastError();
-        if (err == hipSuccess) err = hipMemcpyAsync(host_out.data(), e.out, KT * sizeof(double), hipMemcpyDeviceToHost, s);
+        err = enqueue_multi_fp32c(c, d, th + s0, nth, c->blk.base, zero_skip, out, 1, pi_dev, s);
+        if (err == hipSuccess) err = hipMemcpyAsync(host_out.data(), out, nth * sizeof(double), hipMemcpyDeviceToHost, s);
         if (err == hipSuccess && out_pi)
-            err = hipMemcpyAsync(host_pi.data(), e.pi_out, (size_t)KT * d.n * sizeof(double), hipMemcpyDeviceToHost, s);
+            err = hipMemcpyAsync(host_pi.data(), pi_dev, (size_t)nth * d.n * sizeof(double), hipMemcpyDeviceToHost, s);
         if (err == hipSuccess) err = hipStreamSynchronize(s);
         if (err != hipSuccess) break;
         for (int q = 0; q < nth; ++q) {

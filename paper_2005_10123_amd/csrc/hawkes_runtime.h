@@ -91,6 +91,7 @@ struct hawkes_ctx {
     hawkes::Server* server = nullptr;
     int scheme = hawkes::kSymmetric;  // how pair terms are enumerated (hawkes_set_pair_scheme)
     bool zero_skip = false;           // zero-tile skipping (hawkes_set_zero_tile_skipping)
+    bool shared_passes = false;       // served FP32C log-likelihoods in multi-parameter passes
     int sym_slots[2][2] = {{0, 0}, {0, 0}};  // [precision][grad] resident blocks of the symmetric kernel
     int multi_slots = 0;                     // resident blocks of the multi-parameter kernel
 };
@@ -136,6 +137,14 @@ hawkes_status enqueue_eval(hawkes_ctx* c, const Dataset& d, const hawkes_params&
 hawkes_status blocking_eval(hawkes_ctx* c, int32_t id, const hawkes_params* p, int precision, bool grad,
                             double out7[7], double* host_rows);
 int multi_blocks_per_cu();
+// The FP32C multi-parameter pass (hawkes_multi.hip): up to kMultiTheta parameter vectors share each
+// pair's differences; a vector's result does not depend on the vectors sharing its pass.
+constexpr int kMultiTheta = 4;
+size_t multi_scratch_bytes(const hawkes_ctx* c, const Dataset& d, bool zero_skip, bool want_pi);
+// One pass over nth (1 to kMultiTheta) vectors on stream s: ell of vector q to out[q * out_stride]
+// (device), pi (sorted order) to pi_out[q * n + i] when pi_out is set.
+hipError_t enqueue_multi_fp32c(const hawkes_ctx* c, const Dataset& d, const hawkes_params* th, int nth, char* scratch,
+                               bool zero_skip, double* out, int out_stride, double* pi_out, hipStream_t s);
 
 // hawkes_grad_device_noalloc: the fixed device array holding its evaluation scratch (256 MiB on
 // every device the library runs on), and the per-device lookup of that array's address, done once

@@ -723,6 +723,15 @@ hawkes_status hawkes_set_zero_tile_skipping(hawkes_ctx* c, int enable)
     return HAWKES_OK;
 }
 
+hawkes_status hawkes_set_shared_passes(hawkes_ctx* c, int enable)
+{
+    if (!c) return fail(HAWKES_EINVAL, "ctx is NULL");
+    if (enable != 0 && enable != 1) return fail(HAWKES_EINVAL, "enable must be 0 or 1, not %d", enable);
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->shared_passes = enable != 0;
+    return HAWKES_OK;
+}
+
 hawkes_status hawkes_profile(hawkes_ctx* c, int enable)
 {
     if (!c) return fail(HAWKES_EINVAL, "ctx is NULL");

@@ -7,12 +7,20 @@
 //     admitted request gets a scratch buffer from a pool (its partial sums and block partials);
 //   * packs admitted requests of one kind (precision, with/without gradient) into one launch of
 //     the three evaluation kernels -- the work items of all requests in a launch share the grid;
+//   * evaluates FP32C log-likelihood requests (no gradient: the requests of Algorithm 1's chains)
+//     through the multi-parameter pass when hawkes_set_shared_passes turned that on: the launch's requests on one dataset share passes of up to
+//     kMultiTheta parameter vectors (each pair's differences formed once for all of them), and every
+//     such request, alone or grouped, gets that pass's result for its vector, which does not depend
+//     on the vectors sharing the pass (with zero-tile skipping on, which tiles a pass leaves out
+//     depends on all its vectors, so each request then has a pass of its own);
 //   * issues each launch on the next of several streams, so a launch built from requests that
 //     arrived while earlier ones were running overlaps them on the device;
 //   * reaps finished launches by event query, returns the scratch to the pool and publishes the
 //     results for hawkes_poll.
-// Every request is evaluated with the plan of its own (n, gradient) and its own scratch, so its
-// result is bitwise the same alone, blocking or in any mix.
+// Every request is evaluated with the plan of its own (n, gradient) and its own scratch (or its
+// pass's), so its result is bitwise the same alone or in any mix: with the gradient, and in FP64,
+// the blocking call's; FP32C log-likelihoods, hawkes_loglik_multi's for that vector (equal to the
+// blocking call's to rounding).
 #include "hawkes_runtime.h"
 
 #include <algorithm>
@@ -137,7 +145,8 @@ void reap(hawkes_ctx* c, Server* sv)
                 res[k] = make_result(L.req[k], st);
                 if (st == HAWKES_OK) {
                     res[k].loglik = L.h_out[8 * k];
-                    for (int p = 0; p < 6; ++p) res[k].grad[p] = L.h_out[8 * k + 1 + p];
+                    if (L.req[k].req.want_grad)
+                        for (int p = 0; p < 6; ++p) res[k].grad[p] = L.h_out[8 * k + 1 + p];
                 }
                 sv->pool[L.buf[k]].busy = false;
                 if (Dataset* d = find_dataset(c, L.req[k].req.dataset)) d->inflight -= 1;
@@ -164,6 +173,97 @@ bool any_busy(Server* sv)
     return false;
 }
 
+// Launch FP32C log-likelihood requests (`cand`, arrival order) as multi-parameter passes: requests
+// on one dataset in groups of up to kMultiTheta (one without zero-tile skipping), each group with
+// one pool buffer, its requests contiguous in L.req and their results at d_out + 8 k.  Returns false
+// when the launch could not start everything (requests waiting for memory go back to the queue).
+bool admit_shared(hawkes_ctx* c, Server* sv, Launch& L, const std::vector<Pending>& cand)
+{
+    struct Group {
+        Dataset* d = nullptr;
+        int first = 0, count = 0, buf = -1;
+        hawkes_params th[kMultiTheta];
+    };
+    std::vector<Group> groups;
+    std::vector<Pending> back;
+    std::vector<hawkes_result> failed;
+    int nb = 0;
+    bool zero_skip = false;
+    hipStream_t s = sv->streams[sv->next_stream];
+    hipError_t e = hipSuccess;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        zero_skip = c->zero_skip;
+        const int per_pass = zero_skip ? 1 : kMultiTheta;
+        // Group by dataset, keeping arrival order within each dataset.
+        std::vector<std::vector<const Pending*>> by_ds;
+        std::vector<Dataset*> ds;
+        for (const Pending& p : cand) {
+            Dataset* d = find_dataset(c, p.req.dataset);
+            if (!d) {
+                failed.push_back(make_result(p, HAWKES_ENOTFOUND));
+                continue;
+            }
+            size_t k = 0;
+            while (k < ds.size() && ds[k] != d) ++k;
+            if (k == ds.size()) {
+                ds.push_back(d);
+                by_ds.emplace_back();
+            }
+            by_ds[k].push_back(&p);
+        }
+        for (size_t k = 0; k < ds.size(); ++k)
+            for (size_t a = 0; a < by_ds[k].size(); a += per_pass) {
+                Group g;
+                g.d = ds[k];
+                g.count = (int)std::min<size_t>(per_pass, by_ds[k].size() - a);
+                const size_t need = multi_scratch_bytes(c, *g.d, zero_skip, false);
+                g.buf = back.empty() ? get_buffer(c, sv, need) : -1;
+                if (g.buf < 0) {
+                    for (int q = 0; q < g.count; ++q) {
+                        const Pending& p = *by_ds[k][a + q];
+                        if (!back.empty() || nb > 0 || sv->admitted > 0 || any_busy(sv)) {
+                            back.push_back(p);  // wait for memory held by running work
+                        } else {
+                            g.d->inflight -= 1;
+                            failed.push_back(make_result(p, HAWKES_ENOMEM));
+                        }
+                    }
+                    continue;
+                }
+                sv->pool[g.buf].busy = true;
+                g.first = nb;
+                for (int q = 0; q < g.count; ++q) {
+                    L.req[nb] = *by_ds[k][a + q];
+                    L.buf[nb] = g.buf;
+                    g.th[q] = L.req[nb].req.p;
+                    ++nb;
+                }
+                groups.push_back(g);
+            }
+        for (const Group& g : groups) {
+            e = enqueue_multi_fp32c(c, *g.d, g.th, g.count, sv->pool[g.buf].s.base, zero_skip, L.d_out + 8 * g.first, 8,
+                                    nullptr, s);
+            if (e != hipSuccess) break;
+        }
+    }
+    if (!failed.empty()) publish(sv, failed.data(), (int)failed.size());
+    if (!back.empty()) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (auto it = back.rbegin(); it != back.rend(); ++it) sv->pending.push_front(*it);
+    }
+    if (nb == 0) return back.empty();
+    sv->next_stream = (sv->next_stream + 1) % kStreams;
+    if (e == hipSuccess) e = hipMemcpyAsync(L.h_out, L.d_out, (size_t)nb * 8 * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipEventRecord(L.done, s);
+    L.nreq = nb;
+    sv->admitted += nb;
+    L.busy = true;
+    L.failed = e != hipSuccess;  // reaped as a device failure on the next pass
+    if (L.failed) (void)hipStreamSynchronize(s);
+    return back.empty();
+}
+
 // Admit and launch as much queued work as slots and budget allow.
 void admit(hawkes_ctx* c, Server* sv)
 {
@@ -171,22 +271,58 @@ void admit(hawkes_ctx* c, Server* sv)
         const int li = free_launch(sv);
         if (li < 0 || sv->admitted >= kMaxAdmitted) return;
         Launch& L = sv->launches[li];
+        bool shared = false, zero_skip_now = false;
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            shared = c->shared_passes;
+            zero_skip_now = c->zero_skip;
+        }
         std::vector<Pending> cand;
+        bool shared_kind = false;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
             if (sv->pending.empty()) return;
             // The head request decides the kind of this launch; later requests of the same kind
             // join it (up to kMaxBatch); requests of other kinds keep their place in the queue.
+            // For shared passes, a queued request joins its dataset's pass while that holds fewer
+            // than kMultiTheta vectors, and starts a new one only while the launch has room.
             const int prec = sv->pending.front().req.precision, grad = sv->pending.front().req.want_grad;
-            for (auto it = sv->pending.begin(); it != sv->pending.end() && (int)cand.size() < kMaxBatch;) {
+            shared_kind = shared && prec == HAWKES_FP32C && !grad;
+            const int per_pass = zero_skip_now ? 1 : kMultiTheta;
+            std::vector<std::pair<int32_t, int>> passes;  // (dataset, requests in its open pass)
+            int slots = 0;                                 // requests the launch's passes can hold
+            for (auto it = sv->pending.begin(); it != sv->pending.end();) {
+                bool take = false;
                 if (it->req.precision == prec && it->req.want_grad == grad &&
                     sv->admitted + (int)cand.size() < kMaxAdmitted) {
+                    if (!shared_kind) {
+                        take = (int)cand.size() < kMaxBatch;
+                    } else {
+                        auto ps = std::find_if(passes.begin(), passes.end(), [&](const std::pair<int32_t, int>& q) {
+                            return q.first == it->req.dataset && q.second < per_pass;
+                        });
+                        if (ps != passes.end()) {
+                            ps->second += 1;
+                            take = true;
+                        } else if (slots + per_pass <= kMaxBatch) {
+                            passes.emplace_back(it->req.dataset, 1);
+                            slots += per_pass;
+                            take = true;
+                        }
+                    }
+                }
+                if (take) {
                     cand.push_back(*it);
                     it = sv->pending.erase(it);
                 } else {
                     ++it;
                 }
+                if (!shared_kind && (int)cand.size() >= kMaxBatch) break;
             }
+        }
+        if (shared_kind && !cand.empty()) {
+            if (!admit_shared(c, sv, L, cand)) return;
+            continue;
         }
         PairBatch pb;
         EpiBatch eb;

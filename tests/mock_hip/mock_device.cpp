@@ -23,6 +23,7 @@
 #include <thread>
 
 #include "hawkes_internal.h"
+#include "hawkes_runtime.h"
 
 namespace {
 
@@ -104,6 +105,13 @@ MockStream* stream_of(hipStream_t s) { return s ? s : &g_null_stream; }
 }  // namespace
 
 extern "C" {
+std::atomic<int> g_multi_passes{0}, g_multi_vectors{0}, g_multi_max_nth{0};
+void mock_multi_counts(int* passes, int* vectors, int* max_nth)
+{
+    *passes = g_multi_passes.load();
+    *vectors = g_multi_vectors.load();
+    *max_nth = g_multi_max_nth.load();
+}
 void mock_set_latency_us(int us) { g_latency_ns = (int64_t)us * 1000; }
 void mock_fail_launches(int k) { g_fail_launches = k; }
 int mock_stamp_errors() { return g_stamp_errors.load(); }
@@ -263,7 +271,7 @@ int sym_blocks_per_cu(int precision, bool) { return precision == 0 ? 2 : 3; }
 int multi_blocks_per_cu() { return 2; }
 
 // The fixed-scratch entry point (hawkes_noalloc.hip) is device code only; its set-up call is a no-op here.
-int32_t noalloc_init(int) { return 0; }
+hawkes_status noalloc_init(int) { return HAWKES_OK; }
 
 hipError_t launch_epilogue(const EpiBatch& b, hipStream_t)
 {
@@ -277,6 +285,27 @@ hipError_t launch_epilogue(const EpiBatch& b, hipStream_t)
         if (e.sums_out)
             for (long long i = 0; i < (long long)e.n * 6; ++i) e.sums_out[i] = 0.0;
     }
+    return hipSuccess;
+}
+
+// The multi-parameter pass: its scratch is one stamped row-partial area per pass; the stand-in
+// result of vector q (ell = n + mu0) goes to out[q * out_stride].
+size_t multi_scratch_bytes(const hawkes_ctx*, const Dataset& d, bool, bool) { return (size_t)(d.n + 64) * sizeof(double); }
+
+hipError_t enqueue_multi_fp32c(const hawkes_ctx*, const Dataset& d, const hawkes_params* th, int nth, char* scratch,
+                               bool, double* out, int out_stride, double*, hipStream_t s)
+{
+    if (g_fail_launches.load() > 0 && g_fail_launches.fetch_sub(1) > 0) return hipErrorLaunchFailure;
+    g_multi_passes += 1;
+    g_multi_vectors += nth;
+    int m = g_multi_max_nth.load();
+    while (nth > m && !g_multi_max_nth.compare_exchange_weak(m, nth)) {
+    }
+    double* part = (double*)scratch;
+    part[0] = stamp((int)d.n, th[0].mu0);
+    stream_of(s)->advance(g_latency_ns.load());
+    if (part[0] != stamp((int)d.n, th[0].mu0)) g_stamp_errors += 1;
+    for (int q = 0; q < nth; ++q) out[(size_t)q * out_stride] = (double)d.n + th[q].mu0;
     return hipSuccess;
 }
 

@@ -29,6 +29,7 @@ int mock_stamp_errors();
 long long mock_device_bytes();
 long long mock_peak_device_bytes();
 void mock_reset_peak();
+void mock_multi_counts(int* passes, int* vectors, int* max_nth);
 }
 
 namespace {
@@ -141,6 +142,55 @@ void basic_mix()
     int64_t out = -1;
     check(hawkes_outstanding(c, &out) == HAWKES_OK && out == 0, "nothing outstanding");
     check(mock_stamp_errors() == 0, "scratch of each request is its own");
+    check(hawkes_destroy(c) == HAWKES_OK, "destroy");
+}
+
+// FP32C log-likelihood requests share multi-parameter passes: queued behind a slow launch, 40
+// requests over two datasets go out in passes of up to four vectors of one dataset; with shared
+// passes off they take the single-parameter path; with zero-tile skipping on, one pass each.
+void shared_passes()
+{
+    hawkes_ctx* c = nullptr;
+    check(hawkes_create(0, 0, nullptr, &c) == HAWKES_OK, "create");
+    const int64_t sizes[2] = {4000, 9000};
+    const int32_t ds[2] = {make_dataset(c, sizes[0], 30), make_dataset(c, sizes[1], 31)};
+    mock_set_latency_us(2000);
+    check(hawkes_set_shared_passes(c, 1) == HAWKES_OK, "shared on");
+    int p0 = 0, v0 = 0, m0 = 0;
+    mock_multi_counts(&p0, &v0, &m0);
+    std::vector<hawkes_request> reqs;
+    reqs.push_back(request(ds[1], HAWKES_FP32C, 1, 0.0, 0));  // occupies the device first
+    for (uint64_t tag = 1; tag <= 40; ++tag) reqs.push_back(request(ds[tag % 2], HAWKES_FP32C, 0, 1e-3 * tag, tag));
+    check(hawkes_submit(c, reqs.data(), (int32_t)reqs.size()) == HAWKES_OK, "submit");
+    auto got = collect(c, reqs.size());
+    check(got.size() == reqs.size(), "all results arrived");
+    for (const auto& r : got) check(matches(r, reqs[r.tag], sizes[reqs[r.tag].dataset == ds[1]]), "shared result");
+    int p1 = 0, v1 = 0, m1 = 0;
+    mock_multi_counts(&p1, &v1, &m1);
+    check(v1 - v0 == 40, "every log-likelihood request went through a shared pass");
+    check(p1 - p0 < 40 && m1 <= 4 && m1 >= 2, "requests grouped, at most four per pass");
+    // Shared passes off: the single-parameter path.
+    check(hawkes_set_shared_passes(c, 0) == HAWKES_OK, "shared off");
+    reqs.clear();
+    for (uint64_t tag = 0; tag < 10; ++tag) reqs.push_back(request(ds[tag % 2], HAWKES_FP32C, 0, 1e-3 * tag, tag));
+    check(hawkes_submit(c, reqs.data(), (int32_t)reqs.size()) == HAWKES_OK, "submit");
+    got = collect(c, reqs.size());
+    for (const auto& r : got) check(matches(r, reqs[r.tag], sizes[reqs[r.tag].dataset == ds[1]]), "unshared result");
+    int p2 = 0, v2 = 0, m2 = 0;
+    mock_multi_counts(&p2, &v2, &m2);
+    check(v2 == v1, "no shared pass with shared passes off");
+    // Zero-tile skipping on: one vector per pass.
+    check(hawkes_set_shared_passes(c, 1) == HAWKES_OK && hawkes_set_zero_tile_skipping(c, 1) == HAWKES_OK, "settings");
+    reqs.clear();
+    reqs.push_back(request(ds[1], HAWKES_FP32C, 1, 0.0, 0));
+    for (uint64_t tag = 1; tag <= 12; ++tag) reqs.push_back(request(ds[tag % 2], HAWKES_FP32C, 0, 1e-3 * tag, tag));
+    check(hawkes_submit(c, reqs.data(), (int32_t)reqs.size()) == HAWKES_OK, "submit");
+    got = collect(c, reqs.size());
+    for (const auto& r : got) check(matches(r, reqs[r.tag], sizes[reqs[r.tag].dataset == ds[1]]), "skipping result");
+    int p3 = 0, v3 = 0, m3 = 0;
+    mock_multi_counts(&p3, &v3, &m3);
+    check(v3 - v2 == 12 && p3 - p2 == 12, "one vector per pass with zero-tile skipping");
+    mock_set_latency_us(200);
     check(hawkes_destroy(c) == HAWKES_OK, "destroy");
 }
 
@@ -417,6 +467,7 @@ int main()
 {
     run("basic_mix", basic_mix);
     run("blocking_beside_serving", blocking_beside_serving);
+    run("shared_passes", shared_passes);
     run("tiny_budget_queues", tiny_budget_queues);
     run("column_scratch_by_precision", column_scratch_by_precision);
     run("too_large_fails_alone", too_large_fails_alone);

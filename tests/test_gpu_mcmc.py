@@ -1,5 +1,7 @@
 """Algorithm 1 chains driven through the serving API: many chains in flight, each result equal to
-the blocking evaluation, and the whole run reproducible from the seeds."""
+the blocking evaluation (with shared passes on: to the multi-parameter pass's value for its
+vector, within rounding of the blocking evaluation), and the whole run reproducible from the
+seeds."""
 import numpy as np
 import pytest
 
@@ -15,8 +17,10 @@ def run(ctx, dss, seeds, steps):
     return chains, served
 
 
-def test_served_chains_reproducible_and_exact():
+@pytest.mark.parametrize("shared", [False, True])
+def test_served_chains_reproducible_and_exact(shared):
     ctx = binding.Context(0)
+    ctx.set_shared_passes(shared)
     dss = [ctx.dataset(*synth.simulate(synth.SimSpec(n, 10.0, 1000.0, 3, 0.5, 0.1, 0.3, (10123, 50, k))))
            for k, n in enumerate([2000, 3000])]
     seeds = list(range(100, 108))
@@ -28,7 +32,12 @@ def test_served_chains_reproducible_and_exact():
         assert np.array_equal(np.array(ca.samples), np.array(cb.samples))
         assert 0 < ca.accepted < 60
     for k, ch in enumerate(a):
-        assert ch.loglik == ctx.loglik(dss[k % 2], ch.theta, "fp32c")
+        blocking = ctx.loglik(dss[k % 2], ch.theta, "fp32c")
+        if shared:
+            assert ch.loglik == ctx.loglik_multi(dss[k % 2], [ch.theta], "fp32c", want_pi=False)[0]
+            assert abs(ch.loglik - blocking) <= 1e-7 * abs(blocking)
+        else:
+            assert ch.loglik == blocking
     for d in dss:
         d.close()
     ctx.close()

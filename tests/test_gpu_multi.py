@@ -64,3 +64,23 @@ def test_multi_posterior_regime_minute_scale():
         assert np.max(np.abs(pi[s] - ref["row_pi"])) <= 1e-5, s
     ds.close()
     ctx.close()
+
+
+def test_vector_result_independent_of_pass_mates():
+    """A parameter vector's log-likelihood and probabilities are bitwise the same whether its pass
+    holds 1, 2, 3 or 4 vectors (and whatever the others are): the serving scheduler relies on it to
+    give a request the same result alone and grouped."""
+    x, y, t = synth.simulate(synth.SimSpec(7000, 10.0, 1000.0, 3, 0.5, 0.1, 0.3, (10123, 61, 0)))
+    rng = np.random.default_rng(5)
+    thetas = np.array(synth.THETA_CFG1) * np.exp(0.1 * rng.standard_normal((7, 6)))
+    with binding.Context(0) as ctx:
+        ds = ctx.dataset(x, y, t)
+        ll1, pi1 = ctx.loglik_multi(ds, thetas[:1], "fp32c")
+        for S in (2, 3, 4, 5, 7):
+            ll, pi = ctx.loglik_multi(ds, thetas[:S], "fp32c")
+            assert ll[0] == ll1[0] and np.array_equal(pi[0], pi1[0]), S
+        # The same vector in the middle of other passes.
+        mixed = np.vstack([thetas[3:6], thetas[:1]])
+        ll, pi = ctx.loglik_multi(ds, mixed, "fp32c")
+        assert ll[3] == ll1[0] and np.array_equal(pi[3], pi1[0])
+        ds.close()

@@ -1,6 +1,7 @@
 """Batched serving through hawkes_submit / hawkes_poll: each result matches the FP64 oracle and
-equals the blocking evaluation alone (bitwise: same plan, same arithmetic) whatever it is batched
-with; invalid requests fail
+is bitwise the same alone and whatever it is batched with: equal to the blocking evaluation (same
+plan, same arithmetic), or, with shared passes on, for FP32C log-likelihoods (evaluated in shared
+multi-parameter passes) to hawkes_loglik_multi's value for that vector; invalid requests fail
 alone; a small HBM budget queues work instead of failing; destroying a busy dataset is refused;
 destroying the context with requests in flight is clean; several threads may submit at once."""
 import numpy as np
@@ -179,6 +180,42 @@ def test_submit_from_many_threads():
     for k in range(64):
         assert got[k].status == 0
         assert got[k].loglik == want[k][0] and np.array_equal(np.array(got[k].grad[:]), want[k][1]), k
+    for d in dss:
+        d.close()
+    ctx.close()
+
+
+def test_shared_passes_alone_equal_grouped():
+    """FP32C log-likelihood requests (the requests of Algorithm 1's chains) on one dataset share
+    multi-parameter passes: 4 requests on each of two datasets submitted at once (grouped four per
+    pass), then each again alone; every result is bitwise the same both ways, equal to
+    hawkes_loglik_multi for its vector, and within the FP32C tolerance of the oracle."""
+    ctx = binding.Context(0)
+    ctx.set_shared_passes(True)
+    dss, evs = datasets(ctx, [6000, 11000], seed0=47, events=True)
+    rng = np.random.default_rng(12)
+    thetas = np.array(synth.THETA_CFG1) * np.exp(0.1 * rng.standard_normal((8, 6)))
+    reqs = [binding.request(dss[k % 2], thetas[k], "fp32c", False, tag=k) for k in range(8)]
+    ctx.submit(reqs)
+    grouped = drain(ctx, 8)
+    alone = {}
+    for k in range(8):
+        ctx.submit([binding.request(dss[k % 2], thetas[k], "fp32c", False, tag=100 + k)])
+        alone.update(drain(ctx, 1))
+    for k in range(8):
+        a, g = alone[100 + k], grouped[k]
+        assert a.status == 0 and g.status == 0
+        assert a.loglik == g.loglik, (k, a.loglik, g.loglik)
+        assert g.loglik == ctx.loglik_multi(dss[k % 2], [thetas[k]], "fp32c", want_pi=False)[0]
+        ref = oracle.evaluate_parallel(*evs[k % 2], thetas[k])
+        assert rel(g.loglik, ref["ell"]) <= TOL["fp32c"], (k, g.loglik, ref["ell"])
+        assert rel(g.loglik, ctx.loglik(dss[k % 2], thetas[k], "fp32c")) <= 1e-7, k
+    # Shared passes off (the default): the single-parameter pass, bitwise the blocking call.
+    ctx.set_shared_passes(False)
+    ctx.submit(reqs)
+    plain = drain(ctx, 8)
+    for k in range(8):
+        assert plain[k].loglik == ctx.loglik(dss[k % 2], thetas[k], "fp32c"), k
     for d in dss:
         d.close()
     ctx.close()

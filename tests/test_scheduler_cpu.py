@@ -19,7 +19,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2005_10123_amd", "csrc")
 MOCK = os.path.join(ROOT, "tests", "mock_hip")
 CLANG = "/opt/rocm/llvm/bin/clang++"
-SCENARIOS = ["basic_mix", "blocking_beside_serving", "tiny_budget_queues", "column_scratch_by_precision",
+SCENARIOS = ["basic_mix", "blocking_beside_serving", "shared_passes", "tiny_budget_queues", "column_scratch_by_precision",
              "too_large_fails_alone",
              "invalid_requests_fail_alone", "busy_dataset", "many_threads", "device_failure_poisons",
              "destroy_in_flight"]
