@@ -38,7 +38,7 @@ CUS, CLOCK = 256, 2.4e9
 P_OPS32 = 157.3e12 / 2          # FP32 vector: 157.3 TFLOP/s with FMA = 2 FLOP
 P_OPS64 = 78.6e12 / 2           # FP64 vector
 P_EXP32 = CUS * 32 * CLOCK      # v_exp_f32 lanes per second (32 per CU per clock, measured)
-FP64_EXP_OPS = 16               # FP64 lane operations of one exp2 (range reduction + degree-11 poly)
+FP64_EXP_OPS = 15               # FP64 lane operations of one exp2 (range reduction + degree-10 poly)
 
 
 KERNEL_SOURCES = ("hawkes_kernels.hip", "hawkes_device.h", "hawkes_internal.h")

@@ -1,9 +1,9 @@
 """Coefficients of the binary64 2^f polynomial in hawkes_device.h (exp2_f64).
 
-Remez exchange for the polynomial p of degree 11 that minimises max |(2^f - p(f)) / 2^f| over
+Remez exchange for the polynomial p of degree 10 that minimises max |(2^f - p(f)) / 2^f| over
 f in [-1/2, 1/2], in 60-digit mpmath arithmetic; prints the coefficients (highest degree first)
 rounded to binary64 and the maximal relative error of the rounded polynomial on a fine grid.
-Run: python3 exp2_minimax.py  (needs mpmath).
+Run: python3 exp2_minimax.py [degree]  (needs mpmath; degree 10 by default).
 """
 import mpmath as mp
 
@@ -37,7 +37,9 @@ def remez(deg, a=-0.5, b=0.5, iters=30, grid_points=4000):
 
 
 if __name__ == "__main__":
-    deg = 11
+    import sys
+
+    deg = int(sys.argv[1]) if len(sys.argv) > 1 else 10
     c = [mp.mpf(float(v)) for v in remez(deg)]
     pts = [mp.mpf(-0.5) + mp.mpf(k) / 20000 for k in range(20001)]
     worst = max(abs((mp.power(2, x) - mp.polyval(c[::-1], x)) / mp.power(2, x)) for x in pts)

@@ -48,26 +48,25 @@ __device__ __forceinline__ void two_sum_into(float& s, float& c, float p)
 }
 
 // 2^a in binary64 for a <= 0 (a = -inf allowed).  Range reduction a = k + f, k = rint(a),
-// |f| <= 1/2, then 2^f by the degree-11 polynomial that minimises the maximal relative error on
-// [-1/2, 1/2] (Remez exchange, exp2_minimax.py; 3.4e-17 relative with the coefficients rounded to
-// binary64, below the rounding of the Horner evaluation), scaled by 2^k.  Arguments below -1100
-// give exactly 0.
+// |f| <= 1/2, then 2^f by the degree-10 polynomial that minimises the maximal relative error on
+// [-1/2, 1/2] (Remez exchange, exp2_minimax.py; 2.8e-16 relative with the coefficients rounded to
+// binary64, about the rounding of the Horner evaluation itself), scaled by 2^k.  Arguments below
+// -1100 give exactly 0.
 __device__ __forceinline__ double exp2_f64(double a)
 {
     a = fmax(a, -1100.0);
     const double k = rint(a);
     const double f = a - k;
-    double p = 4.43138940123033412484e-10;
-    p = fma(p, f, 7.07390645602150607471e-09);
-    p = fma(p, f, 1.01782190361934708864e-07);
-    p = fma(p, f, 1.32154346232020881375e-06);
-    p = fma(p, f, 1.52527334528178733073e-05);
-    p = fma(p, f, 1.54035304585322497346e-04);
-    p = fma(p, f, 1.33335581468151023049e-03);
-    p = fma(p, f, 9.61812910759227840396e-03);
-    p = fma(p, f, 5.55041086648198483955e-02);
-    p = fma(p, f, 2.40226506959101443472e-01);
-    p = fma(p, f, 6.93147180559945286227e-01);
+    double p = 7.03735743919096230754e-09;
+    p = fma(p, f, 1.02085352821412315164e-07);
+    p = fma(p, f, 1.32156624055817323250e-06);
+    p = fma(p, f, 1.52526581335867644459e-05);
+    p = fma(p, f, 1.54035299619204323106e-04);
+    p = fma(p, f, 1.33335582285240734912e-03);
+    p = fma(p, f, 9.61812910803399277737e-03);
+    p = fma(p, f, 5.55041086644591438737e-02);
+    p = fma(p, f, 2.40226506959087704463e-01);
+    p = fma(p, f, 6.93147180559949727119e-01);
     p = fma(p, f, 1.0);
     return ldexp(p, (int)k);
 }

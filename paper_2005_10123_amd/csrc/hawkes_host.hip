@@ -23,7 +23,7 @@ namespace hawkes {
 namespace {
 
 // 2^a for a <= 0: a = k + f with k = round(a) (adding 1.5 * 2^52 rounds a to an integer, which
-// then sits in the low bits of the sum's significand), |f| <= 1/2, the degree-11 polynomial
+// then sits in the low bits of the sum's significand), |f| <= 1/2, the degree-10 polynomial
 // minimising the maximal relative error of 2^f on [-1/2, 1/2] (the same Remez fit as the device's
 // binary64 exponential, csrc/exp2_minimax.py), and 2^k written into the exponent field from the
 // sum's bits with integer adds and shifts (no double-to-integer conversion, which has no vector
@@ -36,17 +36,16 @@ inline double exp2_host(double a)
     const double sum = ac + big;
     const double kd = sum - big;
     const double f = ac - kd;
-    double p = 4.43138940123033412484e-10;
-    p = p * f + 7.07390645602150607471e-09;
-    p = p * f + 1.01782190361934708864e-07;
-    p = p * f + 1.32154346232020881375e-06;
-    p = p * f + 1.52527334528178733073e-05;
-    p = p * f + 1.54035304585322497346e-04;
-    p = p * f + 1.33335581468151023049e-03;
-    p = p * f + 9.61812910759227840396e-03;
-    p = p * f + 5.55041086648198483955e-02;
-    p = p * f + 2.40226506959101443472e-01;
-    p = p * f + 6.93147180559945286227e-01;
+    double p = 7.03735743919096230754e-09;
+    p = p * f + 1.02085352821412315164e-07;
+    p = p * f + 1.32156624055817323250e-06;
+    p = p * f + 1.52526581335867644459e-05;
+    p = p * f + 1.54035299619204323106e-04;
+    p = p * f + 1.33335582285240734912e-03;
+    p = p * f + 9.61812910803399277737e-03;
+    p = p * f + 5.55041086644591438737e-02;
+    p = p * f + 2.40226506959087704463e-01;
+    p = p * f + 6.93147180559949727119e-01;
     p = p * f + 1.0;
     unsigned long long sb;
     std::memcpy(&sb, &sum, sizeof sb);
