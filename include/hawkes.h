@@ -115,8 +115,8 @@ hawkes_status hawkes_grad_device(hawkes_ctx* ctx, int32_t id, const hawkes_param
  * the library holds on every device it runs on until the process ends, not memory of the context:
  * this call makes no device or host allocation (its address is looked up once per device by
  * hawkes_create).  Limit: an evaluation whose scratch exceeds 256 MiB fails with HAWKES_ENOMEM
- * before anything is enqueued (symmetric enumeration: up to about 155,000 events with FP32C, about
- * 120,000 with FP64; the direct enumeration's scratch grows linearly in n).  Every call on one GPU,
+ * before anything is enqueued (symmetric enumeration: up to about 110,000 events with FP32C, about
+ * 99,000 with FP64; the direct enumeration's scratch grows linearly in n).  Every call on one GPU,
  * from any context or thread, shares that array: calls whose device work overlaps (different
  * streams not ordered with each other, or another context on the same GPU) race and give wrong
  * results; calls on one stream, or on streams the caller orders, are safe.  The array keeps the

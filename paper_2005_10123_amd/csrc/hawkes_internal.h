@@ -126,7 +126,7 @@ struct EpiBatch {
 // the arithmetic nor the summation order, and the result stays deterministic.
 constexpr long long kDynDiv = 8;
 constexpr long long kDynMinUnitsPerBlock = 4;  // smaller walks keep the static split only
-constexpr int kDynChunksPerBlock = 2;          // the host plan's cap on dchunks, per block
+constexpr int kDynChunksPerBlock = 32;         // the host plan's cap on dchunks, per block
 
 struct WalkSplit {
     long long sunits;       // walk positions [0, sunits) are dealt statically: block b walks
