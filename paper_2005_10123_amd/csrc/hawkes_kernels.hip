@@ -370,11 +370,7 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
             for (int r = 0; r < R; ++r) p[k][r] = 0.0f;
 #pragma unroll 1
         for (int g = ch; g < ch + kChunk; g += 4) {
-            float cp[3][4];
-#pragma unroll
-            for (int q = 0; q < 3; ++q)
-#pragma unroll
-                for (int cc = 0; cc < 4; ++cc) cp[q][cc] = 0.0f;
+            float cp[3][4];  // set by each column's first row (no additions of zero)
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) {
                 const float4 hi = sj[2 * (g + cc)];
@@ -399,12 +395,22 @@ __device__ __forceinline__ void sym_tile_fp32(const float4* __restrict__ sj, int
                         if (MODE == kDiag) ab = (j < lrow0 + r) ? ab : -INFINITY;
                         const float b = __builtin_amdgcn_exp2f(ab);
                         p[0][r] += b;
-                        cp[0][cc] += b;
                         if (GRAD) {
                             p[1][r] = fmaf(r2, b, p[1][r]);
                             p[2][r] = fmaf(dt2, b, p[2][r]);
-                            cp[1][cc] = fmaf(r2, b, cp[1][cc]);
-                            cp[2][cc] = fmaf(dt2, b, cp[2][cc]);
+                        }
+                        if (r == 0) {
+                            cp[0][cc] = b;
+                            if (GRAD) {
+                                cp[1][cc] = r2 * b;
+                                cp[2][cc] = dt2 * b;
+                            }
+                        } else {
+                            cp[0][cc] += b;
+                            if (GRAD) {
+                                cp[1][cc] = fmaf(r2, b, cp[1][cc]);
+                                cp[2][cc] = fmaf(dt2, b, cp[2][cc]);
+                            }
                         }
                     }
                     if (DO_E) {
@@ -753,11 +759,7 @@ __device__ __forceinline__ void sym_tile_fp64(const double4* __restrict__ sj, in
             for (int k4 = 0; k4 < 4; ++k4) colw[qq * kTile + 4 * lane + k4] = 0.0;
 #pragma unroll 1
     for (int g = 0; g < kTile; g += 4) {
-        double cp[3][4];
-#pragma unroll
-        for (int q = 0; q < 3; ++q)
-#pragma unroll
-            for (int cc = 0; cc < 4; ++cc) cp[q][cc] = 0.0;
+        double cp[3][4];  // set by each column's first row (no additions of zero)
 #pragma unroll
         for (int cc = 0; cc < 4; ++cc) {
             const double4 e = sj[g + cc];
@@ -774,12 +776,22 @@ __device__ __forceinline__ void sym_tile_fp64(const double4* __restrict__ sj, in
                     if (MODE == kDiag) ab = (j < lrow0 + r) ? ab : -INFINITY;
                     const double b = exp2_f64(ab);
                     a[0][r] += b;
-                    cp[0][cc] += b;
                     if (GRAD) {
                         a[1][r] = fma(r2, b, a[1][r]);
                         a[2][r] = fma(dt2, b, a[2][r]);
-                        cp[1][cc] = fma(r2, b, cp[1][cc]);
-                        cp[2][cc] = fma(dt2, b, cp[2][cc]);
+                    }
+                    if (r == 0) {
+                        cp[0][cc] = b;
+                        if (GRAD) {
+                            cp[1][cc] = r2 * b;
+                            cp[2][cc] = dt2 * b;
+                        }
+                    } else {
+                        cp[0][cc] += b;
+                        if (GRAD) {
+                            cp[1][cc] = fma(r2, b, cp[1][cc]);
+                            cp[2][cc] = fma(dt2, b, cp[2][cc]);
+                        }
                     }
                 }
                 if (DO_E) {

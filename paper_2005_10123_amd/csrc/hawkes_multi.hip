@@ -81,11 +81,7 @@ __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0
             for (int r = 0; r < R; ++r) p[k][r] = 0.0f;
 #pragma unroll 1
         for (int g = ch; g < ch + kChunk; g += 4) {
-            float cp[KT][4];
-#pragma unroll
-            for (int q = 0; q < KT; ++q)
-#pragma unroll
-                for (int cc = 0; cc < 4; ++cc) cp[q][cc] = 0.0f;
+            float cp[KT][4];  // set by each column's first row (no additions of zero)
 #pragma unroll
             for (int cc = 0; cc < 4; ++cc) {
                 const float4 hi = sj[2 * (g + cc)];
@@ -107,7 +103,7 @@ __device__ __forceinline__ void multi_tile(const float4* __restrict__ sj, int j0
                         if (MODE == kDiag) ab = below ? ab : -INFINITY;
                         const float b = __builtin_amdgcn_exp2f(ab);
                         p[2 * q][r] += b;
-                        cp[q][cc] += b;
+                        cp[q][cc] = r == 0 ? b : cp[q][cc] + b;
                         float ae = fmaf(r2, nae[q], dt * nbe[q]);
                         if (MODE != kFullLow) ae = causal ? ae : -INFINITY;
                         p[2 * q + 1][r] += __builtin_amdgcn_exp2f(ae);
