@@ -143,8 +143,10 @@ __device__ __forceinline__ double dpp_d(double v)
 {
     const uint2 u = __builtin_bit_cast(uint2, v);
     uint2 r;
-    r.x = (unsigned)__builtin_amdgcn_update_dpp(0, (int)u.x, CTRL, 0xF, 0xF, false);
-    r.y = (unsigned)__builtin_amdgcn_update_dpp(0, (int)u.y, CTRL, 0xF, 0xF, false);
+    // No "old" operand: a rotation reads a valid lane everywhere, and an old value of zero would
+    // cost a move per half and level (binary64 additions take no DPP operand to fuse it into).
+    r.x = (unsigned)__builtin_amdgcn_mov_dpp((int)u.x, CTRL, 0xF, 0xF, false);
+    r.y = (unsigned)__builtin_amdgcn_mov_dpp((int)u.y, CTRL, 0xF, 0xF, false);
     return __builtin_bit_cast(double, r);
 }
 
